@@ -1,0 +1,214 @@
+"""CPU oracle for the space-variant box-spline filter -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (``paper_1109_5114_amd``)
+never imports it, and it never imports the product path.
+
+The arithmetic lives in ``bsf_oracle.c`` (plain C, FP64 and exact integers),
+written from the definitions of Chaudhury & Sanyal (arXiv:1109.5114):
+Box_a and the box spline as a convolution of line boxes (Section 1.1,
+eq. boxSpline), the running-sum recursion (Alg. 3 step 2) and the
+space-variant filtering integral (Section 2.1).  This module only marshals
+numpy arrays to it.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+U8, U16, F32 = 1, 2, 3
+INT, REAL = 0, 1
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        l, i, d = ctypes.c_long, ctypes.c_int, ctypes.c_double
+        L.bsfo_weights_real.argtypes = [d, P, i]
+        L.bsfo_dweights_real.argtypes = [d, P, i]
+        L.bsfo_weights_int.argtypes = [l, P, i]
+        L.bsfo_kernel_real.argtypes = [i, P, P, P, P, P, P, P, P, l]
+        L.bsfo_kernel_int.argtypes = [i, P, P, P, P, P, P, P, P, l]
+        L.bsfo_filter.argtypes = [P, i, l, l, l, i, P, i, i, i, P, l, P, P, P, P, i]
+        L.bsfo_grad_real.argtypes = [P, l, l, l, i, P, i, i, P, P, P, l, l, l, l, l, P, P, i]
+        L.bsfo_preintegrate.argtypes = [P, i, l, l, l, i, P, i, i, l, l, l, l, P]
+        L.bsfo_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _dtype_code(img):
+    if img.dtype == np.uint8:
+        return U8
+    if img.dtype == np.uint16:
+        return U16
+    if img.dtype == np.float32:
+        return F32
+    raise TypeError("oracle images are uint8, uint16 or float32")
+
+
+def num_threads():
+    return lib().bsfo_num_threads()
+
+
+def weights_real(s):
+    """1-D factor weights w_s(i), i = -h..h, for a continuous step s."""
+    buf = np.zeros(4096)
+    h = lib().bsfo_weights_real(float(s), _p(buf), 4096)
+    return np.arange(-h, h + 1), buf[: 2 * h + 1].copy()
+
+
+def dweights_real(s):
+    buf = np.zeros(4096)
+    h = lib().bsfo_dweights_real(float(s), _p(buf), 4096)
+    return np.arange(-h, h + 1), buf[: 2 * h + 1].copy()
+
+
+def weights_int(s):
+    buf = np.zeros(4096, dtype=np.int64)
+    h = lib().bsfo_weights_int(int(s), _p(buf), 4096)
+    return np.arange(-h, h + 1), buf[: 2 * h + 1].copy()
+
+
+def _factor_dirs(fdirs):
+    fd = np.ascontiguousarray(np.asarray(fdirs, dtype=np.int32).reshape(-1, 2))
+    return np.ascontiguousarray(fd[:, 0]), np.ascontiguousarray(fd[:, 1])
+
+
+def kernel_real(fdirs, steps):
+    """Normalised kernel of one pixel: factor j has direction fdirs[j] and
+    continuous step steps[j].  Returns (x0, y0, K) with K[b, a] the weight of
+    the offset (x0 + a, y0 + b)."""
+    dx, dy = _factor_dirs(fdirs)
+    s = np.ascontiguousarray(np.asarray(steps, dtype=np.float64))
+    M = len(s)
+    ext = np.zeros(4, dtype=np.int64)
+    L = lib()
+    rc = L.bsfo_kernel_real(M, _p(dx), _p(dy), _p(s), _p(ext[0:]), ext[1:].ctypes.data,
+                            ext[2:].ctypes.data, ext[3:].ctypes.data, None, 0)
+    if rc:
+        raise ValueError(rc)
+    x0, y0, w, h = (int(v) for v in ext)
+    K = np.zeros((h, w))
+    rc = L.bsfo_kernel_real(M, _p(dx), _p(dy), _p(s), _p(ext[0:]), ext[1:].ctypes.data,
+                            ext[2:].ctypes.data, ext[3:].ctypes.data, _p(K), K.size)
+    if rc:
+        raise ValueError(rc)
+    return x0, y0, K
+
+
+def kernel_int(fdirs, steps):
+    """Unnormalised integer-step kernel (sample counts) of one pixel."""
+    dx, dy = _factor_dirs(fdirs)
+    s = np.ascontiguousarray(np.asarray(steps, dtype=np.int64))
+    M = len(s)
+    ext = np.zeros(4, dtype=np.int64)
+    L = lib()
+    rc = L.bsfo_kernel_int(M, _p(dx), _p(dy), _p(s), _p(ext[0:]), ext[1:].ctypes.data,
+                           ext[2:].ctypes.data, ext[3:].ctypes.data, None, 0)
+    if rc:
+        raise ValueError(rc)
+    x0, y0, w, h = (int(v) for v in ext)
+    K = np.zeros((h, w), dtype=np.int64)
+    rc = L.bsfo_kernel_int(M, _p(dx), _p(dy), _p(s), _p(ext[0:]), ext[1:].ctypes.data,
+                           ext[2:].ctypes.data, ext[3:].ctypes.data, _p(K), K.size)
+    if rc:
+        raise ValueError(rc)
+    return x0, y0, K
+
+
+def filter(img, dirs, order, tied, mode, steps, pix=None, threads=0, want_int=False):
+    """Space-variant box-spline filter, FP64 (and exact num/den for integer
+    images in integer-step mode when want_int).  img [H][W]; steps
+    [planes][H][W] float32; pix: optional flat pixel indices.  Returns out, or
+    (out, num, den)."""
+    img = np.ascontiguousarray(img)
+    H, W = img.shape
+    dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1))
+    steps = np.ascontiguousarray(steps, dtype=np.float32)
+    planes = (len(dirs) // 2) if tied else (len(dirs) // 2) * order
+    assert steps.shape == (planes, H, W), steps.shape
+    if pix is not None:
+        pix = np.ascontiguousarray(np.asarray(pix, dtype=np.int64).reshape(-1))
+        count = len(pix)
+    else:
+        count = H * W
+    out = np.zeros(count)
+    num = np.zeros(count, dtype=np.int64) if want_int else None
+    den = np.zeros(count, dtype=np.int64) if want_int else None
+    rc = lib().bsfo_filter(_p(img), _dtype_code(img), H, W, W, len(dirs) // 2, _p(dirs),
+                           order, int(bool(tied)), mode, _p(steps),
+                           count if pix is not None else 0, _p(pix), _p(out), _p(num), _p(den),
+                           int(threads))
+    if rc == -2:
+        raise ValueError("invalid step (below 1, or non-integer in integer mode)")
+    if rc:
+        raise ValueError(rc)
+    if pix is None:
+        out = out.reshape(H, W)
+        if want_int:
+            num, den = num.reshape(H, W), den.reshape(H, W)
+    return (out, num, den) if want_int else out
+
+
+def grad_real(img, dirs, order, tied, steps, gout, window=None, pix=None, want_img=True,
+              want_steps=True, threads=0):
+    """FP64 gradients of sum(gout * out) for continuous steps.
+
+    grad_img [H][W]: contributions of the output pixels inside window
+    (x0, x1, y0, y1) (default: all).  grad_steps: [planes][H][W], or
+    [n][planes] when pix is given."""
+    img = np.ascontiguousarray(img, dtype=np.float32)
+    H, W = img.shape
+    dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1))
+    n_dirs = len(dirs) // 2
+    steps = np.ascontiguousarray(steps, dtype=np.float32)
+    gout = np.ascontiguousarray(gout, dtype=np.float32)
+    planes = n_dirs if tied else n_dirs * order
+    gi = np.zeros((H, W)) if want_img else None
+    if window is None:
+        window = (0, W, 0, H)
+    x0, x1, y0, y1 = window
+    if pix is not None:
+        pix = np.ascontiguousarray(np.asarray(pix, dtype=np.int64).reshape(-1))
+        count = len(pix)
+    else:
+        count = H * W
+    gs = np.zeros((count, planes)) if want_steps else None
+    rc = lib().bsfo_grad_real(_p(img), H, W, W, n_dirs, _p(dirs), order, int(bool(tied)),
+                              _p(steps), _p(gout), _p(gi), x0, x1, y0, y1,
+                              count if pix is not None else 0, _p(pix), _p(gs), int(threads))
+    if rc:
+        raise ValueError(rc)
+    if want_steps and pix is None:
+        gs = gs.T.reshape(planes, H, W).copy()
+    return gi, gs
+
+
+def preintegrate(img, dirs, order, F, pads):
+    """Running sums on the window; pads = (top, bottom, left, right).  Returns
+    uint64 G [H + top + bottom][W + left + right]."""
+    img = np.ascontiguousarray(img)
+    H, W = img.shape
+    dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1))
+    pt, pb, pl, pr = pads
+    G = np.zeros((H + pt + pb, W + pl + pr), dtype=np.uint64)
+    rc = lib().bsfo_preintegrate(_p(img), _dtype_code(img), H, W, W, len(dirs) // 2, _p(dirs),
+                                 order, int(F), pt, pb, pl, pr, _p(G))
+    if rc:
+        raise ValueError(rc)
+    return G

@@ -1,0 +1,532 @@
+/*
+ * bsf_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow CPU implementation of the space-variant box-spline filter of
+ * K. N. Chaudhury and S. Sanyal, "Improvements on 'Fast space-variant elliptical
+ * filtering using box splines'" (arXiv:1109.5114).  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It shares
+ * no code, header, table or helper with the GPU library; the two meet only
+ * through the seeded inputs and the documented array layouts.
+ *
+ * Everything here is written from the definitions, in the order the paper states
+ * them, without blocking, fusion or reordering:
+ *
+ *   - the box distribution Box_a (Section 1.1): 1/a on the half-open interval
+ *     (-a/2, a/2], zero elsewhere;
+ *   - the box spline as the convolution of boxes laid along lattice directions
+ *     (eq. boxSpline), here with one box per factor j along the integer
+ *     direction u_j and a per-pixel length s_j(x) counted in lattice steps;
+ *   - the pre-integration by running sums along each direction (Section 1.1,
+ *     first step of BoxFilter; Alg. 3 step 2 gives the recursion form
+ *     g(p) = f(p) + g(p - u));
+ *   - the filter output as the image convolved with the pixel's own box spline,
+ *     i.e. the space-variant filtering integral of Section 2.1.
+ *
+ * Readings of points the paper leaves open (each is listed in the design notes):
+ *   - Continuous (non-integer) steps: each box of length s is integrated over the
+ *     unit cells of the lattice line, w_s(i) = |[i-1/2, i+1/2] ^ [-s/2, s/2]|.
+ *     This is the exact result of reading the running sum linearly between
+ *     lattice points along u_j, the one-direction restriction of the box-spline
+ *     interpolation of eq. interpolation.
+ *   - Integer steps: the half-open Box_s used as a convolution kernel, so an
+ *     even length puts its extra sample on the -u side.
+ *   - Steps are in lattice steps along u_j, the running sums carry no sqrt(5)
+ *     (or sqrt(2)) weight, and the output divides by the product of the steps.
+ *   - The image is zero outside [0,W) x [0,H).
+ *
+ * Pins: every function below is checked by the "not gpu" tests against closed
+ * forms (mass, mean, covariance, discrete-time Fourier transform), brute-force
+ * enumeration on tiny inputs and textbook special cases.
+ *
+ * Layouts (shared with the GPU library only as documented interfaces):
+ *   image  [H][pitch] row-major; x = column (0..W-1), y = row (0..H-1)
+ *   dirs   n_dirs pairs (dx, dy), u = (dx, dy) in (column, row) units
+ *   steps  [planes][H][W] float32; factor j (0 <= j < n_dirs*order) lies along
+ *          direction j / order and reads plane (tied ? j / order : j)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { BSFO_U8 = 1, BSFO_U16 = 2, BSFO_F32 = 3 };
+enum { BSFO_INT = 0, BSFO_REAL = 1 };
+
+#define BSFO_MAX_FACTORS 16
+
+/* Read one image sample as a double; zero outside the image (zero extension). */
+static double img_at(const void *img, int dtype, long H, long W, long pitch, long x, long y)
+{
+    if (x < 0 || y < 0 || x >= W || y >= H) return 0.0;
+    switch (dtype) {
+    case BSFO_U8: return (double)((const uint8_t *)img)[y * pitch + x];
+    case BSFO_U16: return (double)((const uint16_t *)img)[y * pitch + x];
+    default: return (double)((const float *)img)[y * pitch + x];
+    }
+}
+
+static __int128 img_at_int(const void *img, int dtype, long H, long W, long pitch, long x, long y)
+{
+    if (x < 0 || y < 0 || x >= W || y >= H) return 0;
+    if (dtype == BSFO_U8) return ((const uint8_t *)img)[y * pitch + x];
+    return ((const uint16_t *)img)[y * pitch + x];
+}
+
+/* ------------------------------------------------------------------------- */
+/* One box factor, as 1-D weights over lattice offsets i in [-h, h].          */
+/* ------------------------------------------------------------------------- */
+
+/* Continuous step s > 0: the length-s box integrated over the unit cell around
+ * each lattice point, w_s(i) = |[i-1/2, i+1/2] ^ [-s/2, s/2]|.  Returns h. */
+int bsfo_weights_real(double s, double *w, int cap)
+{
+    int h = (int)floor(s / 2.0 + 0.5) + 1;
+    if (2 * h + 1 > cap) return -1;
+    for (int i = -h; i <= h; i++) {
+        double lo = fmax(i - 0.5, -s / 2.0);
+        double hi = fmin(i + 0.5, s / 2.0);
+        w[i + h] = hi > lo ? hi - lo : 0.0;
+    }
+    return h;
+}
+
+/* Derivative of w_s(i) with respect to s (right derivative at cell edges): the
+ * two end cells, the ones holding +s/2 and -s/2, each gain 1/2. */
+int bsfo_dweights_real(double s, double *dw, int cap)
+{
+    int h = (int)floor(s / 2.0 + 0.5) + 1;
+    if (2 * h + 1 > cap) return -1;
+    for (int i = -h; i <= h; i++) {
+        double d = 0.0;
+        if (i - 0.5 <= s / 2.0 && s / 2.0 < i + 0.5) d += 0.5;     /* cell holding +s/2 */
+        if (i - 0.5 < -s / 2.0 && -s / 2.0 <= i + 0.5) d += 0.5;   /* cell holding -s/2 */
+        dw[i + h] = d;
+    }
+    return h;
+}
+
+/* Integer step s >= 1: the unnormalised half-open box (-s/2, s/2] as a
+ * convolution kernel.  Convolution places the sample at offset -t for each
+ * t in the box, so the weight at offset i is 1 when -s/2 < -i <= s/2. */
+int bsfo_weights_int(long s, int64_t *w, int cap)
+{
+    int h = (int)(s / 2) + 1;
+    if (2 * h + 1 > cap) return -1;
+    for (int i = -h; i <= h; i++) {
+        long t = -i;
+        /* -s/2 < t <= s/2, tested in integers as -s < 2t <= s */
+        w[i + h] = (-s < 2 * t && 2 * t <= s) ? 1 : 0;
+    }
+    return h;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The 2-D kernel of one pixel: convolution of its line boxes (eq. boxSpline). */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    long x0, y0, w, h;   /* kernel value for offset (x0 + a, y0 + b) at k[b*w + a] */
+    double *k;
+} kern_f64;
+
+typedef struct {
+    long x0, y0, w, h;
+    int64_t *k;
+} kern_i64;
+
+/* Convolve a 2-D kernel with 1-D weights wt[-hw..hw] laid along (dx, dy). */
+static void conv_line_f64(kern_f64 *K, int dx, int dy, const double *wt, int hw)
+{
+    long ex = (long)hw * labs(dx), ey = (long)hw * labs(dy);
+    kern_f64 N;
+    N.x0 = K->x0 - ex; N.y0 = K->y0 - ey;
+    N.w = K->w + 2 * ex; N.h = K->h + 2 * ey;
+    N.k = (double *)calloc((size_t)(N.w * N.h), sizeof(double));
+    for (long b = 0; b < K->h; b++)
+        for (long a = 0; a < K->w; a++) {
+            double v = K->k[b * K->w + a];
+            if (v == 0.0) continue;
+            long px = K->x0 + a, py = K->y0 + b;
+            for (int i = -hw; i <= hw; i++) {
+                double wi = wt[i + hw];
+                if (wi == 0.0) continue;
+                long qx = px + (long)i * dx, qy = py + (long)i * dy;
+                N.k[(qy - N.y0) * N.w + (qx - N.x0)] += wi * v;
+            }
+        }
+    free(K->k);
+    *K = N;
+}
+
+static void conv_line_i64(kern_i64 *K, int dx, int dy, const int64_t *wt, int hw)
+{
+    long ex = (long)hw * labs(dx), ey = (long)hw * labs(dy);
+    kern_i64 N;
+    N.x0 = K->x0 - ex; N.y0 = K->y0 - ey;
+    N.w = K->w + 2 * ex; N.h = K->h + 2 * ey;
+    N.k = (int64_t *)calloc((size_t)(N.w * N.h), sizeof(int64_t));
+    for (long b = 0; b < K->h; b++)
+        for (long a = 0; a < K->w; a++) {
+            int64_t v = K->k[b * K->w + a];
+            if (v == 0) continue;
+            long px = K->x0 + a, py = K->y0 + b;
+            for (int i = -hw; i <= hw; i++) {
+                int64_t wi = wt[i + hw];
+                if (wi == 0) continue;
+                long qx = px + (long)i * dx, qy = py + (long)i * dy;
+                N.k[(qy - N.y0) * N.w + (qx - N.x0)] += wi * v;
+            }
+        }
+    free(K->k);
+    *K = N;
+}
+
+/* Factor j's step at pixel index pidx. */
+static double step_of(const float *steps, long HW, int order, int tied, int j, long pidx)
+{
+    int plane = tied ? j / order : j;
+    return (double)steps[(long)plane * HW + pidx];
+}
+
+/* Unnormalised continuous-step kernel of one pixel: the convolution over all
+ * factors of w_{s_j}.  If dplane >= 0, the factors reading that step plane are
+ * differentiated one at a time and the results summed (product rule). */
+static kern_f64 pixel_kernel_real(int M, const int *fdx, const int *fdy, const double *s,
+                                  const int *fplane, int dplane)
+{
+    double *wt = (double *)malloc(sizeof(double) * 4096);
+    kern_f64 acc = {0, 0, 1, 1, NULL};
+    acc.k = (double *)calloc(1, sizeof(double));
+    if (dplane < 0) {
+        acc.k[0] = 1.0;
+        for (int j = 0; j < M; j++) {
+            int h = bsfo_weights_real(s[j], wt, 4096);
+            conv_line_f64(&acc, fdx[j], fdy[j], wt, h);
+        }
+        free(wt);
+        return acc;
+    }
+    /* sum over the differentiated factor d of (dw_d * prod_{j != d} w_j) */
+    for (int d = 0; d < M; d++) {
+        if (fplane[d] != dplane) continue;
+        kern_f64 t = {0, 0, 1, 1, NULL};
+        t.k = (double *)calloc(1, sizeof(double));
+        t.k[0] = 1.0;
+        for (int j = 0; j < M; j++) {
+            int h = (j == d) ? bsfo_dweights_real(s[j], wt, 4096) : bsfo_weights_real(s[j], wt, 4096);
+            conv_line_f64(&t, fdx[j], fdy[j], wt, h);
+        }
+        /* acc += t, on the union bounding box */
+        long x0 = acc.x0 < t.x0 ? acc.x0 : t.x0, y0 = acc.y0 < t.y0 ? acc.y0 : t.y0;
+        long x1 = (acc.x0 + acc.w > t.x0 + t.w) ? acc.x0 + acc.w : t.x0 + t.w;
+        long y1 = (acc.y0 + acc.h > t.y0 + t.h) ? acc.y0 + acc.h : t.y0 + t.h;
+        kern_f64 u = {x0, y0, x1 - x0, y1 - y0, NULL};
+        u.k = (double *)calloc((size_t)(u.w * u.h), sizeof(double));
+        for (long b = 0; b < acc.h; b++)
+            for (long a = 0; a < acc.w; a++)
+                u.k[(acc.y0 + b - y0) * u.w + (acc.x0 + a - x0)] += acc.k[b * acc.w + a];
+        for (long b = 0; b < t.h; b++)
+            for (long a = 0; a < t.w; a++)
+                u.k[(t.y0 + b - y0) * u.w + (t.x0 + a - x0)] += t.k[b * t.w + a];
+        free(acc.k); free(t.k);
+        acc = u;
+    }
+    free(wt);
+    return acc;
+}
+
+static kern_i64 pixel_kernel_int(int M, const int *fdx, const int *fdy, const long *s)
+{
+    int64_t *wt = (int64_t *)malloc(sizeof(int64_t) * 4096);
+    kern_i64 acc = {0, 0, 1, 1, NULL};
+    acc.k = (int64_t *)calloc(1, sizeof(int64_t));
+    acc.k[0] = 1;
+    for (int j = 0; j < M; j++) {
+        int h = bsfo_weights_int(s[j], wt, 4096);
+        conv_line_i64(&acc, fdx[j], fdy[j], wt, h);
+    }
+    free(wt);
+    return acc;
+}
+
+/* Exported for the closed-form tests: the normalised continuous-step kernel
+ * (divided by the product of the steps), written into k[h][w] with its origin
+ * offset.  Call with k == NULL to get the extents only. */
+int bsfo_kernel_real(int M, const int *fdx, const int *fdy, const double *s,
+                     long *x0, long *y0, long *w, long *h, double *k, long cap)
+{
+    int fplane[BSFO_MAX_FACTORS];
+    if (M < 1 || M > BSFO_MAX_FACTORS) return -1;
+    for (int j = 0; j < M; j++) fplane[j] = j;
+    kern_f64 K = pixel_kernel_real(M, fdx, fdy, s, fplane, -1);
+    double den = 1.0;
+    for (int j = 0; j < M; j++) den *= s[j];
+    *x0 = K.x0; *y0 = K.y0; *w = K.w; *h = K.h;
+    if (k) {
+        if (K.w * K.h > cap) { free(K.k); return -2; }
+        for (long i = 0; i < K.w * K.h; i++) k[i] = K.k[i] / den;
+    }
+    free(K.k);
+    return 0;
+}
+
+/* Exported: the unnormalised integer-step kernel (sample counts). */
+int bsfo_kernel_int(int M, const int *fdx, const int *fdy, const long *s,
+                    long *x0, long *y0, long *w, long *h, int64_t *k, long cap)
+{
+    if (M < 1 || M > BSFO_MAX_FACTORS) return -1;
+    kern_i64 K = pixel_kernel_int(M, fdx, fdy, s);
+    *x0 = K.x0; *y0 = K.y0; *w = K.w; *h = K.h;
+    if (k) {
+        if (K.w * K.h > cap) { free(K.k); return -2; }
+        memcpy(k, K.k, sizeof(int64_t) * (size_t)(K.w * K.h));
+    }
+    free(K.k);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The filter: each output pixel is the image convolved with its own kernel.  */
+/* ------------------------------------------------------------------------- */
+
+static int factor_layout(int n_dirs, const int *dirs, int order, int tied, int *fdx, int *fdy, int *fplane)
+{
+    int M = n_dirs * order;
+    if (n_dirs < 1 || order < 1 || M > BSFO_MAX_FACTORS) return -1;
+    for (int j = 0; j < M; j++) {
+        fdx[j] = dirs[2 * (j / order)];
+        fdy[j] = dirs[2 * (j / order) + 1];
+        fplane[j] = tied ? j / order : j;
+    }
+    return M;
+}
+
+/*
+ * out[n]  = filtered value at pixel pix[n] (or at every pixel when pix == NULL),
+ *           in FP64: sum_p k(p) f(x + p) / prod_j s_j.
+ * num/den = for integer images in integer-step mode, the exact numerator
+ *           sum_p k(p) f(x + p) and denominator prod_j s_j (nullable).
+ * Returns 0, or a negative code for bad arguments (non-integer step in integer
+ * mode, step below 1).
+ */
+int bsfo_filter(const void *img, int dtype, long H, long W, long pitch,
+                int n_dirs, const int *dirs, int order, int tied, int mode,
+                const float *steps, long n_pix, const long *pix,
+                double *out, int64_t *num, int64_t *den, int n_threads)
+{
+    int fdx[BSFO_MAX_FACTORS], fdy[BSFO_MAX_FACTORS], fplane[BSFO_MAX_FACTORS];
+    int M = factor_layout(n_dirs, dirs, order, tied, fdx, fdy, fplane);
+    if (M < 0) return -1;
+    long HW = H * W;
+    long count = pix ? n_pix : HW;
+    int bad = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (long n = 0; n < count; n++) {
+        long pidx = pix ? pix[n] : n;
+        long x = pidx % W, y = pidx / W;
+        double s[BSFO_MAX_FACTORS];
+        for (int j = 0; j < M; j++) s[j] = step_of(steps, HW, order, tied, j, pidx);
+        if (mode == BSFO_INT) {
+            long si[BSFO_MAX_FACTORS];
+            __int128 d = 1;
+            for (int j = 0; j < M; j++) {
+                if (s[j] < 1.0 || s[j] != floor(s[j])) { bad = 1; si[j] = 1; }
+                else si[j] = (long)s[j];
+                d *= si[j];
+            }
+            kern_i64 K = pixel_kernel_int(M, fdx, fdy, si);
+            if (dtype == BSFO_F32) {
+                double acc = 0.0;
+                for (long b = 0; b < K.h; b++)
+                    for (long a = 0; a < K.w; a++) {
+                        int64_t kv = K.k[b * K.w + a];
+                        if (kv) acc += (double)kv * img_at(img, dtype, H, W, pitch, x + K.x0 + a, y + K.y0 + b);
+                    }
+                if (out) out[n] = acc / (double)d;
+                if (num) num[n] = 0;
+            } else {
+                __int128 acc = 0;
+                for (long b = 0; b < K.h; b++)
+                    for (long a = 0; a < K.w; a++) {
+                        int64_t kv = K.k[b * K.w + a];
+                        if (kv) acc += (__int128)kv * img_at_int(img, dtype, H, W, pitch, x + K.x0 + a, y + K.y0 + b);
+                    }
+                if (out) out[n] = (double)acc / (double)d;
+                if (num) num[n] = (int64_t)acc;
+            }
+            if (den) den[n] = (int64_t)d;
+            free(K.k);
+        } else {
+            double d = 1.0;
+            for (int j = 0; j < M; j++) {
+                if (!(s[j] >= 1.0)) bad = 1;
+                d *= s[j];
+            }
+            kern_f64 K = pixel_kernel_real(M, fdx, fdy, s, fplane, -1);
+            double acc = 0.0;
+            for (long b = 0; b < K.h; b++)
+                for (long a = 0; a < K.w; a++) {
+                    double kv = K.k[b * K.w + a];
+                    if (kv != 0.0) acc += kv * img_at(img, dtype, H, W, pitch, x + K.x0 + a, y + K.y0 + b);
+                }
+            if (out) out[n] = acc / d;
+            if (num) num[n] = 0;
+            if (den) den[n] = 0;
+            free(K.k);
+        }
+    }
+    return bad ? -2 : 0;
+}
+
+/*
+ * Gradients of L = sum_x gout(x) * out(x) for continuous steps, in FP64.
+ *   grad_img[H][W]          = sum_x gout(x) k_x(p - x) / prod s(x)   (adjoint
+ *                             of the space-variant filter; nullable)
+ *   grad_steps[n*planes+q]  = gout(x) * d out(x) / d s_q(x) at pixel pix[n]
+ *                             (or every pixel), plane-major per pixel
+ *                             (nullable).  d out / d s = (sum_p dk(p) f(x+p) -
+ *                             out * d prod s / d s) / prod s.
+ * grad_img is produced by scattering every pixel's kernel, so it is meant for
+ * small images or a window: only pixels x in [gx0,gx1) x [gy0,gy1) contribute.
+ */
+int bsfo_grad_real(const float *img, long H, long W, long pitch,
+                   int n_dirs, const int *dirs, int order, int tied,
+                   const float *steps, const float *gout,
+                   double *grad_img, long gx0, long gx1, long gy0, long gy1,
+                   long n_pix, const long *pix, double *grad_steps, int n_threads)
+{
+    int fdx[BSFO_MAX_FACTORS], fdy[BSFO_MAX_FACTORS], fplane[BSFO_MAX_FACTORS];
+    int M = factor_layout(n_dirs, dirs, order, tied, fdx, fdy, fplane);
+    if (M < 0) return -1;
+    int planes = tied ? n_dirs : M;
+    long HW = H * W;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    if (grad_img) {
+        memset(grad_img, 0, sizeof(double) * (size_t)HW);
+#pragma omp parallel
+        {
+            double *priv = (double *)calloc((size_t)HW, sizeof(double));
+#pragma omp for schedule(dynamic, 4)
+            for (long y = gy0; y < gy1; y++)
+                for (long x = gx0; x < gx1; x++) {
+                    long pidx = y * W + x;
+                    double g = gout[pidx];
+                    if (g == 0.0) continue;
+                    double s[BSFO_MAX_FACTORS], d = 1.0;
+                    for (int j = 0; j < M; j++) { s[j] = step_of(steps, HW, order, tied, j, pidx); d *= s[j]; }
+                    kern_f64 K = pixel_kernel_real(M, fdx, fdy, s, fplane, -1);
+                    for (long b = 0; b < K.h; b++)
+                        for (long a = 0; a < K.w; a++) {
+                            long px = x + K.x0 + a, py = y + K.y0 + b;
+                            if (px < 0 || py < 0 || px >= W || py >= H) continue;
+                            priv[py * W + px] += g * K.k[b * K.w + a] / d;
+                        }
+                    free(K.k);
+                }
+#pragma omp critical
+            for (long i = 0; i < HW; i++) grad_img[i] += priv[i];
+            free(priv);
+        }
+    }
+    if (grad_steps) {
+        long count = pix ? n_pix : HW;
+#pragma omp parallel for schedule(dynamic, 8)
+        for (long n = 0; n < count; n++) {
+            long pidx = pix ? pix[n] : n;
+            long x = pidx % W, y = pidx / W;
+            double s[BSFO_MAX_FACTORS], d = 1.0;
+            for (int j = 0; j < M; j++) { s[j] = step_of(steps, HW, order, tied, j, pidx); d *= s[j]; }
+            kern_f64 K = pixel_kernel_real(M, fdx, fdy, s, fplane, -1);
+            double acc = 0.0;
+            for (long b = 0; b < K.h; b++)
+                for (long a = 0; a < K.w; a++)
+                    acc += K.k[b * K.w + a] * img_at(img, BSFO_F32, H, W, pitch, x + K.x0 + a, y + K.y0 + b);
+            free(K.k);
+            double outv = acc / d;
+            for (int q = 0; q < planes; q++) {
+                kern_f64 D = pixel_kernel_real(M, fdx, fdy, s, fplane, q);
+                double dacc = 0.0;
+                for (long b = 0; b < D.h; b++)
+                    for (long a = 0; a < D.w; a++)
+                        dacc += D.k[b * D.w + a] * img_at(img, BSFO_F32, H, W, pitch, x + D.x0 + a, y + D.y0 + b);
+                free(D.k);
+                /* d(prod s)/d s_q / prod s = (number of factors on plane q) / s_q */
+                int mult = 0;
+                double sq = 0.0;
+                for (int j = 0; j < M; j++) if (fplane[j] == q) { mult++; sq = s[j]; }
+                grad_steps[n * planes + q] = (double)gout[pidx] * (dacc / d - outv * (double)mult / sq);
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Pre-integration (running sums), in exact integers modulo 2^64.             */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * G = (S_{u_N})^order ... (S_{u_1})^order f_q on the window
+ * rows [-pad_top, H + pad_bottom) x cols [-pad_left, W + pad_right), with
+ * f_q = f (integer images) or f_q = nearest-even integer of f * 2^F (float
+ * images), zero outside the image.  Each running sum follows the recursion of
+ * Alg. 3 step 2, g(p) = f(p) + g(p - u), started at zero where a line enters the
+ * window; the passes run in the order the directions are given, and the
+ * arithmetic wraps modulo 2^64.  G is stored [Hp][Wp], with G[(y + pad_top) *
+ * Wp + (x + pad_left)] holding the value at (x, y).
+ */
+int bsfo_preintegrate(const void *img, int dtype, long H, long W, long pitch,
+                      int n_dirs, const int *dirs, int order, int F,
+                      long pad_top, long pad_bottom, long pad_left, long pad_right,
+                      uint64_t *G)
+{
+    long Hp = H + pad_top + pad_bottom, Wp = W + pad_left + pad_right;
+    for (long yy = 0; yy < Hp; yy++)
+        for (long xx = 0; xx < Wp; xx++) {
+            long x = xx - pad_left, y = yy - pad_top;
+            uint64_t q = 0;
+            if (x >= 0 && y >= 0 && x < W && y < H) {
+                if (dtype == BSFO_F32) {
+                    double v = ldexp((double)((const float *)img)[y * pitch + x], F);
+                    q = (uint64_t)(int64_t)nearbyint(v);
+                } else {
+                    q = (uint64_t)(int64_t)img_at_int(img, dtype, H, W, pitch, x, y);
+                }
+            }
+            G[yy * Wp + xx] = q;
+        }
+    for (int k = 0; k < n_dirs; k++) {
+        int dx = dirs[2 * k], dy = dirs[2 * k + 1];
+        for (int rep = 0; rep < order; rep++) {
+            /* Visit points so that p - u is always finished before p: order the
+             * rows along dy and, within a row (dy == 0), the columns along dx. */
+            for (long t = 0; t < Hp; t++) {
+                long yy = dy >= 0 ? t : Hp - 1 - t;
+                for (long c = 0; c < Wp; c++) {
+                    long xx = dx >= 0 ? c : Wp - 1 - c;
+                    long px = xx - dx, py = yy - dy;
+                    if (px < 0 || py < 0 || px >= Wp || py >= Hp) continue;
+                    G[yy * Wp + xx] += G[py * Wp + px];
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+int bsfo_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
