@@ -1,0 +1,249 @@
+/*
+ * bsf.h -- C ABI of libbsf, a space-variant box-spline filter for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The filter is the O(1) space-variant elliptical filter of K. N. Chaudhury and
+ * S. Sanyal, "Improvements on 'Fast space-variant elliptical filtering using box
+ * splines'" (arXiv:1109.5114): one global pre-integration of the image by
+ * running sums along N integer lattice directions (Section 1.1, first step of
+ * BoxFilter; Alg. 3 step 2), followed at every pixel by a signed finite
+ * difference of the running sum whose steps are that pixel's own box lengths
+ * (Section 1.1, second step of BoxFilter; Table 1; Alg. 3 step 3), divided by
+ * the product of the steps (the weight w of Table 1).  "Order r" convolves the
+ * box spline with itself r times (Section 1.2 and Section 2.1: higher-order box
+ * splines), so there are M = N*r box factors per pixel.
+ *
+ * What each pixel computes (x = column, y = row, f = 0 outside the image):
+ *
+ *   integer steps:     out(x) = sum_{i in prod_j I_j} f(x + sum_j i_j u_j) / prod_j s_j
+ *                      with I_j = {c_j - s_j + 1, ..., c_j}, c_j = floor((s_j - 1)/2),
+ *                      the half-open box Box_s of Section 1.1 used as a
+ *                      convolution kernel;
+ *   continuous steps:  out(x) = sum_{i in Z^M} prod_j w_{s_j}(i_j) f(x + sum_j i_j u_j) / prod_j s_j
+ *                      with w_s(i) = |[i - 1/2, i + 1/2] ^ [-s/2, s/2]|, the box of
+ *                      length s integrated over the unit cells of its lattice
+ *                      line.  This equals reading the running sum linearly
+ *                      between lattice points along u_j, the one-direction
+ *                      restriction of the box-spline interpolation of
+ *                      eq. interpolation.
+ *
+ * Arithmetic.  The running sums and the signed tap combination are exact
+ * two's-complement integers modulo 2^64 (BSF_ARITH_EXACT): a float image is
+ * first scaled to fixed point, f_q = nearest-even(f * 2^F); the tap combination
+ * is an integer that is bounded even though the running sums wrap, so it comes
+ * out exact.  Phase weights of continuous steps and the final division are FP64,
+ * rounded once to FP32.  BSF_ARITH_FP64 runs the same method with plain FP64
+ * running sums and FP64 taps; it is provided as the plain baseline and loses
+ * accuracy through cancellation on large images and at order 2.
+ *
+ * Conventions for every entry point:
+ *   - Device pointers unless noted "host".  The caller owns every buffer; the
+ *     library never allocates device memory and never synchronises, except
+ *     bsf_read_device_status which synchronises the given stream.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *   - Images are row-major with a row pitch counted in elements (>= W).
+ *   - Step fields are FP32 [planes][H][W], dense.  planes = N when tied (one
+ *     step per direction, used by its r box factors), N*r when untied (factor
+ *     j = k*r + q lies along direction k and reads plane j).
+ *   - Host-side validation returns BSF_E_* before anything is enqueued.  Values
+ *     found bad on the device (a NaN step, a step below 1 or above max_step, a
+ *     non-integer step in integer mode, a fixed-point overflow bound) raise
+ *     sticky bits in the status word at the start of the workspace, read with
+ *     bsf_read_device_status; the outputs of such pixels are unspecified.
+ *   - Calls that share a workspace must not overlap in time.
+ */
+#ifndef BSF_H
+#define BSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSF_OK = 0,
+    BSF_E_INVALID = 1,     /* bad argument: null pointer, bad direction, pitch < W, ... */
+    BSF_E_RANGE = 2,       /* device status: a step out of range, NaN or non-integer */
+    BSF_E_OVERFLOW = 3,    /* fixed-point headroom cannot hold the tap combination */
+    BSF_E_WORKSPACE = 4,   /* workspace too small */
+    BSF_E_DEVICE = 5,      /* a HIP call failed */
+    BSF_E_UNSUPPORTED = 6  /* valid request outside what this build implements */
+} bsf_status;
+
+typedef enum { BSF_U8 = 1, BSF_U16 = 2, BSF_F32 = 3 } bsf_dtype;
+typedef enum { BSF_STEPS_INT = 0, BSF_STEPS_REAL = 1 } bsf_step_mode;
+typedef enum { BSF_ARITH_EXACT = 0, BSF_ARITH_FP64 = 1 } bsf_arith;
+
+#define BSF_MAX_DIRS 8
+#define BSF_MAX_FACTORS 16
+
+/* Device status bits (bsf_read_device_status). */
+#define BSF_FLAG_RANGE 1u
+#define BSF_FLAG_OVERFLOW 2u
+
+/*
+ * Filter configuration.
+ *   dirs:      n_dirs primitive integer vectors (dx, dy), x = column, y = row,
+ *              in canonical sign (dx > 0, or dx == 0 and dy > 0).  The running
+ *              sums are taken in the order given.  At most one direction may have
+ *              dy < 0 and it must come last: the running sums are kept on a
+ *              finite window, and only the last pass may leave terms behind
+ *              at the window edge (they are constant, or of degree < order, along
+ *              its own direction, so its differences cancel them exactly).
+ *   order:     r >= 1 (box spline convolved r times); n_dirs * order <= 16.
+ *   tied:      1: one step plane per direction, 0: one plane per box factor.
+ *   mode:      BSF_STEPS_INT (integer steps, exact integer output) or
+ *              BSF_STEPS_REAL (continuous steps).
+ *   max_step:  upper bound on every step (>= 1); it sizes the padding of the
+ *              running-sum window.  Steps above it raise BSF_FLAG_RANGE.
+ *   frac_bits: F for float images: >= 0 fixes it, -1 chooses on the device the
+ *              largest F for which the tap combination cannot overflow, from the
+ *              image's largest magnitude and the steps actually present.  Ignored
+ *              for integer images (F = 0) and for BSF_ARITH_FP64.
+ *   arith:     BSF_ARITH_EXACT or BSF_ARITH_FP64.
+ */
+typedef struct {
+    int32_t n_dirs;
+    int32_t dirs[2 * BSF_MAX_DIRS];
+    int32_t order;
+    int32_t tied;
+    int32_t mode;
+    float max_step;
+    int32_t frac_bits;
+    int32_t arith;
+} bsf_config;
+
+/*
+ * Geometry of the running-sum window for a (config, H, W): the window covers
+ * rows [-pad_top, H + pad_bottom) and columns [-pad_left, W + pad_right) so
+ * that every tap of every pixel lands inside it.  G is stored row-major
+ * [win_h][win_w] with 8-byte elements (int64, or double for BSF_ARITH_FP64);
+ * the value at (x, y) sits at G[(y + pad_top) * win_w + (x + pad_left)].
+ * win_w is padded to a multiple of 16 elements.
+ */
+typedef struct {
+    int64_t pad_top, pad_bottom, pad_left, pad_right;
+    int64_t win_h, win_w;
+    size_t g_bytes;          /* win_h * win_w * 8 */
+    size_t workspace_bytes;  /* bytes bsf_filter_varying needs when G is not saved */
+    size_t workspace_bytes_g_external; /* bytes it needs when the caller passes G_save */
+} bsf_geometry;
+
+/*
+ * Enqueues the clearing of the status word at the start of a workspace.  Call
+ * once on every new workspace before its first use (the flags are sticky).
+ */
+bsf_status bsf_workspace_init(void *ws, size_t ws_bytes, void *stream);
+
+/* Host only.  Fills *geo; BSF_E_INVALID for a bad configuration or size. */
+bsf_status bsf_plan(const bsf_config *cfg, int64_t H, int64_t W, bsf_geometry *geo);
+
+/*
+ * Pre-integration alone (Section 1.1, first step; Alg. 3 step 2).
+ *   img:   [H][pitch] of dtype.
+ *   F:     fixed-point bits for float images (0..62); ignored for integer images
+ *          and for BSF_ARITH_FP64.
+ *   G:     output window, bsf_geometry layout (int64 or double by cfg->arith).
+ *   ws:    scratch of at least bsf_geometry.workspace_bytes_g_external bytes.
+ * G = (S_{u_N})^r ... (S_{u_1})^r f_q on the window, each running sum
+ * S_u g(p) = g(p) + S_u g(p - u) started at zero where its line enters the
+ * window, wrapping modulo 2^64.
+ */
+bsf_status bsf_preintegrate(const bsf_config *cfg, bsf_dtype dtype, const void *img,
+                            int64_t H, int64_t W, int64_t pitch, int32_t F,
+                            void *G, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Forward filter (the whole hot path: fixed-point load, running sums, per-pixel
+ * signed taps with the pixel's own steps, exact combination, normalisation).
+ *   steps:   FP32 [planes][H][W].
+ *   out:     FP32 [H][W] (nullable).
+ *   out_num: int64 [H][W] numerators, integer images in integer mode only
+ *            (nullable); out_den: int64 [H][W], prod_j s_j (nullable).
+ *   G_save:  nullable; when given, the running sums are built there (layout of
+ *            bsf_geometry) and left for bsf_filter_backward, and ws needs only
+ *            workspace_bytes_g_external.
+ */
+bsf_status bsf_filter_varying(const bsf_config *cfg, bsf_dtype dtype, const void *img,
+                              int64_t H, int64_t W, int64_t pitch, const float *steps,
+                              float *out, int64_t *out_num, int64_t *out_den,
+                              void *G_save, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The forward filter in its two stages; bsf_filter_varying is exactly
+ * bsf_forward_prepare followed by bsf_forward_apply.
+ *
+ * bsf_forward_prepare: range check of the steps, choice of F (frac_bits), and
+ *   the running sums of img into G (bsf_geometry layout; G == NULL puts them in
+ *   the workspace).  ws: workspace_bytes (G == NULL) or
+ *   workspace_bytes_g_external bytes.
+ * bsf_forward_apply: the per-pixel taps of G with the pixel's steps,
+ *   normalised (Section 1.1, second step of BoxFilter; Alg. 3 step 3).  G and
+ *   ws must come from a bsf_forward_prepare on the same configuration, image
+ *   size and workspace (ws holds F).  The steps may differ from the ones given
+ *   to bsf_forward_prepare (one pre-integration serves several step fields, as
+ *   the two banks of Alg. 2 do); their fixed-point bound is then rechecked on
+ *   the device.  G == NULL reads the running sums from the workspace.
+ */
+bsf_status bsf_forward_prepare(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H,
+                               int64_t W, int64_t pitch, const float *steps, void *G, void *ws,
+                               size_t ws_bytes, void *stream);
+bsf_status bsf_forward_apply(const bsf_config *cfg, bsf_dtype dtype, int64_t H, int64_t W,
+                             const float *steps, const void *G, float *out, int64_t *out_num,
+                             int64_t *out_den, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of the forward filter for FP32 images with continuous steps
+ * (spec differentiation): given the upstream gradient gout [H][W] of a
+ * scalar loss L, writes
+ *   grad_img   [H][W]          dL/df = K^T gout (nullable),
+ *   grad_steps [planes][H][W]  dL/ds (nullable; right derivative where the
+ *                              phase of a step is at a kink).
+ * G_saved: the window left by bsf_filter_varying for the same img, steps and
+ * configuration, or NULL to recompute it.  ws: at least
+ * bsf_backward_workspace_bytes bytes.
+ */
+size_t bsf_backward_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W);
+bsf_status bsf_filter_backward(const bsf_config *cfg, const float *img, int64_t H, int64_t W,
+                               int64_t pitch, const float *steps, const float *gout,
+                               float *grad_img, float *grad_steps, const void *G_saved,
+                               void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Batched forward over B images of uneven sizes (FP32 images, one shared
+ * configuration).  descs is a host array.  Every image's work is enqueued on
+ * `stream`; ws must hold bsf_batched_workspace_bytes.  use_graph = 1 captures
+ * the launches into a HIP graph once per (workspace, descriptor set) and
+ * replays it.
+ */
+typedef struct {
+    const float *img;
+    const float *steps;
+    float *out;
+    int64_t H, W, pitch;
+} bsf_image_desc;
+
+size_t bsf_batched_workspace_bytes(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs);
+bsf_status bsf_filter_batched(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs,
+                              void *ws, size_t ws_bytes, void *stream, int32_t use_graph);
+
+/*
+ * Synchronises `stream`, then copies the status word from the workspace
+ * (host outputs): *flags gets BSF_FLAG_* bits, *F_used the fixed-point bits of
+ * the last forward call, *log2_bound the bound ceil(log2 max|f| + log2 max prod)
+ * it was chosen from.  Any pointer may be NULL.  Clears the flags when clear != 0.
+ */
+bsf_status bsf_read_device_status(void *ws, void *stream, uint32_t *flags, int32_t *F_used,
+                                  int32_t *log2_bound, int32_t clear);
+
+const char *bsf_status_string(bsf_status s);
+
+/* Library version string, e.g. "bsf 0.1 gfx950". */
+const char *bsf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,290 @@
+"""Python binding of libbsf, the MI355X space-variant box-spline filter.
+
+This module only marshals arguments: PyTorch provides device memory and the
+current HIP stream, and every step of the filter runs in the HIP kernels of
+libbsf.so behind the C ABI declared in include/bsf.h.  There is no CPU
+fallback: if the library is missing, importing the ops raises.
+"""
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbsf.so")
+
+OK, E_INVALID, E_RANGE, E_OVERFLOW, E_WORKSPACE, E_DEVICE, E_UNSUPPORTED = range(7)
+U8, U16, F32 = 1, 2, 3
+STEPS_INT, STEPS_REAL = 0, 1
+ARITH_EXACT, ARITH_FP64 = 0, 1
+FLAG_RANGE, FLAG_OVERFLOW = 1, 2
+MAX_DIRS = 8
+DIRS4 = ((1, 0), (0, 1), (1, 1), (1, -1))
+
+
+class BsfError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s: %s" % (what, status_string(code)))
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("n_dirs", ctypes.c_int32), ("dirs", ctypes.c_int32 * (2 * MAX_DIRS)),
+                ("order", ctypes.c_int32), ("tied", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("max_step", ctypes.c_float), ("frac_bits", ctypes.c_int32), ("arith", ctypes.c_int32)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("pad_top", ctypes.c_int64), ("pad_bottom", ctypes.c_int64),
+                ("pad_left", ctypes.c_int64), ("pad_right", ctypes.c_int64),
+                ("win_h", ctypes.c_int64), ("win_w", ctypes.c_int64),
+                ("g_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+                ("workspace_bytes_g_external", ctypes.c_size_t)]
+
+
+class _ImageDesc(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("steps", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("H", ctypes.c_int64), ("W", ctypes.c_int64), ("pitch", ctypes.c_int64)]
+
+
+_lib = None
+
+EXPORTS = ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_varying",
+           "bsf_forward_prepare", "bsf_forward_apply",
+           "bsf_backward_workspace_bytes", "bsf_filter_backward", "bsf_batched_workspace_bytes",
+           "bsf_filter_batched", "bsf_read_device_status", "bsf_status_string", "bsf_version")
+
+
+def lib():
+    """The loaded libbsf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libbsf.so is not built; run paper_1109_5114_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        cfgp = ctypes.POINTER(_Config)
+        L.bsf_workspace_init.argtypes = [P, sz, P]
+        L.bsf_plan.argtypes = [cfgp, i64, i64, ctypes.POINTER(Geometry)]
+        L.bsf_preintegrate.argtypes = [cfgp, i32, P, i64, i64, i64, i32, P, P, sz, P]
+        L.bsf_filter_varying.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, P, P, sz, P]
+        L.bsf_forward_prepare.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, sz, P]
+        L.bsf_forward_apply.argtypes = [cfgp, i32, i64, i64, P, P, P, P, P, P, sz, P]
+        L.bsf_backward_workspace_bytes.argtypes = [cfgp, i64, i64]
+        L.bsf_backward_workspace_bytes.restype = sz
+        L.bsf_filter_backward.argtypes = [cfgp, P, i64, i64, i64, P, P, P, P, P, P, sz, P]
+        L.bsf_batched_workspace_bytes.argtypes = [cfgp, i32, ctypes.POINTER(_ImageDesc)]
+        L.bsf_batched_workspace_bytes.restype = sz
+        L.bsf_filter_batched.argtypes = [cfgp, i32, ctypes.POINTER(_ImageDesc), P, sz, P, i32]
+        L.bsf_read_device_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint32),
+                                             ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
+        L.bsf_status_string.argtypes = [i32]
+        L.bsf_status_string.restype = ctypes.c_char_p
+        L.bsf_version.restype = ctypes.c_char_p
+        for name in ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_varying",
+                     "bsf_forward_prepare", "bsf_forward_apply",
+                     "bsf_filter_backward", "bsf_filter_batched", "bsf_read_device_status"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def status_string(code):
+    try:
+        return lib().bsf_status_string(int(code)).decode()
+    except ImportError:
+        return "status %d" % code
+
+
+def _check(code, what):
+    if code != OK:
+        raise BsfError(code, what)
+
+
+@dataclass(frozen=True)
+class Config:
+    """Filter configuration (mirrors bsf_config)."""
+    dirs: Tuple[Tuple[int, int], ...] = DIRS4
+    order: int = 1
+    tied: bool = True
+    mode: int = STEPS_REAL
+    max_step: float = 16.0
+    frac_bits: int = -1
+    arith: int = ARITH_EXACT
+
+    @property
+    def n_dirs(self):
+        return len(self.dirs)
+
+    @property
+    def planes(self):
+        return self.n_dirs if self.tied else self.n_dirs * self.order
+
+    def c(self):
+        c = _Config()
+        c.n_dirs = len(self.dirs)
+        for k, (dx, dy) in enumerate(self.dirs):
+            c.dirs[2 * k] = int(dx)
+            c.dirs[2 * k + 1] = int(dy)
+        c.order = int(self.order)
+        c.tied = int(bool(self.tied))
+        c.mode = int(self.mode)
+        c.max_step = float(self.max_step)
+        c.frac_bits = int(self.frac_bits)
+        c.arith = int(self.arith)
+        return c
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor):
+    if t.dtype == torch.uint8:
+        return U8
+    if t.dtype == torch.uint16:
+        return U16
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("images are uint8, uint16 or float32, got %s" % t.dtype)
+
+
+def plan(cfg: Config, H: int, W: int) -> Geometry:
+    g = Geometry()
+    _check(lib().bsf_plan(ctypes.byref(cfg.c()), int(H), int(W), ctypes.byref(g)), "bsf_plan")
+    return g
+
+
+class Workspace:
+    """Device scratch owned by the caller (here: a torch uint8 tensor)."""
+
+    def __init__(self, nbytes: int, device="cuda"):
+        self.nbytes = max(int(nbytes), 256)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        _check(lib().bsf_workspace_init(_ptr(self.buf), self.nbytes, _stream(self.buf.device)),
+               "bsf_workspace_init")
+
+    def ensure(self, nbytes: int):
+        if nbytes > self.nbytes:
+            self.__init__(nbytes, self.buf.device)
+        return self
+
+    def ptr(self):
+        return _ptr(self.buf)
+
+    def status(self, clear=False):
+        """Synchronises the current stream; returns (flags, F_used, log2_bound)."""
+        fl, F, b = ctypes.c_uint32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().bsf_read_device_status(self.ptr(), _stream(self.buf.device), ctypes.byref(fl),
+                                            ctypes.byref(F), ctypes.byref(b), int(bool(clear))),
+               "bsf_read_device_status")
+        return fl.value, F.value, b.value
+
+
+_ws_cache = {}
+
+
+def _workspace(device, nbytes):
+    key = (str(device),)
+    ws = _ws_cache.get(key)
+    if ws is None:
+        ws = _ws_cache[key] = Workspace(nbytes, device)
+    return ws.ensure(nbytes)
+
+
+def _check_image(img):
+    if not img.is_cuda or img.dim() != 2:
+        raise ValueError("image must be a 2-D device tensor")
+    if img.stride(1) != 1:
+        raise ValueError("image rows must be contiguous")
+
+
+def _check_steps(cfg, steps, H, W):
+    if steps.dtype != torch.float32 or not steps.is_cuda or not steps.is_contiguous():
+        raise ValueError("steps must be a contiguous float32 device tensor")
+    if tuple(steps.shape) != (cfg.planes, H, W):
+        raise ValueError("steps must have shape %s, got %s" % ((cfg.planes, H, W), tuple(steps.shape)))
+
+
+def preintegrate(cfg: Config, img: torch.Tensor, F: int = 24, ws: Optional[Workspace] = None) -> torch.Tensor:
+    """Running sums on the window; returns the [win_h][win_w] int64 (or float64) tensor."""
+    _check_image(img)
+    H, W = img.shape
+    g = plan(cfg, H, W)
+    dt = torch.float64 if cfg.arith == ARITH_FP64 else torch.int64
+    G = torch.empty((g.win_h, g.win_w), dtype=dt, device=img.device)
+    ws = ws or _workspace(img.device, g.workspace_bytes_g_external)
+    ws.ensure(g.workspace_bytes_g_external)
+    _check(lib().bsf_preintegrate(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, img.stride(0),
+                                  int(F), _ptr(G), ws.ptr(), ws.nbytes, _stream(img.device)),
+           "bsf_preintegrate")
+    return G
+
+
+def filter_varying(cfg: Config, img: torch.Tensor, steps: torch.Tensor, out: Optional[torch.Tensor] = None,
+                   want_num: bool = False, want_den: bool = False, save_G: bool = False,
+                   ws: Optional[Workspace] = None):
+    """Forward space-variant filter.  Returns out (float32 [H][W]) and, on
+    request, num/den (int64, integer-step mode) and the saved window G."""
+    _check_image(img)
+    H, W = img.shape
+    _check_steps(cfg, steps, H, W)
+    g = plan(cfg, H, W)
+    dev = img.device
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    num = torch.empty((H, W), dtype=torch.int64, device=dev) if want_num else None
+    den = torch.empty((H, W), dtype=torch.int64, device=dev) if want_den else None
+    G = None
+    if save_G:
+        G = torch.empty((g.win_h, g.win_w), dtype=torch.float64 if cfg.arith == ARITH_FP64 else torch.int64,
+                        device=dev)
+    need = g.workspace_bytes_g_external if save_G else g.workspace_bytes
+    ws = ws or _workspace(dev, need)
+    ws.ensure(need)
+    _check(lib().bsf_filter_varying(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, img.stride(0),
+                                    _ptr(steps), _ptr(out), _ptr(num), _ptr(den), _ptr(G), ws.ptr(), ws.nbytes,
+                                    _stream(dev)),
+           "bsf_filter_varying")
+    res = [out]
+    if want_num:
+        res.append(num)
+    if want_den:
+        res.append(den)
+    if save_G:
+        res.append(G)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def forward_prepare(cfg: Config, img: torch.Tensor, steps: torch.Tensor, ws: Workspace,
+                    G: Optional[torch.Tensor] = None):
+    """Range check, choice of F and running sums (into G, or into ws when G is None)."""
+    _check_image(img)
+    H, W = img.shape
+    _check_steps(cfg, steps, H, W)
+    _check(lib().bsf_forward_prepare(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, img.stride(0),
+                                     _ptr(steps), _ptr(G), ws.ptr(), ws.nbytes, _stream(img.device)),
+           "bsf_forward_prepare")
+
+
+def forward_apply(cfg: Config, dtype_code: int, steps: torch.Tensor, ws: Workspace, out: torch.Tensor,
+                  G: Optional[torch.Tensor] = None, num: Optional[torch.Tensor] = None,
+                  den: Optional[torch.Tensor] = None):
+    """Per-pixel taps of the running sums left by forward_prepare."""
+    _, H, W = steps.shape
+    _check_steps(cfg, steps, H, W)
+    _check(lib().bsf_forward_apply(ctypes.byref(cfg.c()), int(dtype_code), H, W, _ptr(steps), _ptr(G), _ptr(out),
+                                   _ptr(num), _ptr(den), ws.ptr(), ws.nbytes, _stream(steps.device)),
+           "bsf_forward_apply")
+    return out
+
+
+def version():
+    return lib().bsf_version().decode()

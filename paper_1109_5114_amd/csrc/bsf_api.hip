@@ -1,0 +1,369 @@
+// C ABI of libbsf: validation, planning of the running-sum window, workspace
+// layout and launch sequencing.  Declarations and contracts: include/bsf.h.
+#include <math.h>
+#include <string.h>
+
+#include "bsf_common.h"
+
+namespace bsf {
+
+namespace {
+
+int gcd_int(int a, int b) {
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        int t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+__global__ void k_set_F(int32_t *status, int32_t F) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) status[ST_F_USED] = F;
+}
+
+__global__ void k_clear_status(int32_t *status) {
+    if (blockIdx.x == 0 && threadIdx.x < ST_WORDS) status[threadIdx.x] = 0;
+}
+
+int src_kind_of(bsf_dtype d) {
+    switch (d) {
+    case BSF_U8: return SRC_U8;
+    case BSF_U16: return SRC_U16;
+    case BSF_F32: return SRC_F32;
+    }
+    return -1;
+}
+
+}  // namespace
+
+bsf_status make_plan(const bsf_config *cfg, int64_t H, int64_t W, Plan *p) {
+    if (!cfg || !p) return BSF_E_INVALID;
+    memset(p, 0, sizeof(*p));
+    if (cfg->n_dirs < 1 || cfg->n_dirs > BSF_MAX_DIRS) return BSF_E_INVALID;
+    if (cfg->order < 1) return BSF_E_INVALID;
+    if (cfg->order > 4) return BSF_E_UNSUPPORTED;
+    if (cfg->n_dirs * cfg->order > BSF_MAX_FACTORS) return BSF_E_INVALID;
+    if (cfg->mode != BSF_STEPS_INT && cfg->mode != BSF_STEPS_REAL) return BSF_E_INVALID;
+    if (cfg->arith != BSF_ARITH_EXACT && cfg->arith != BSF_ARITH_FP64) return BSF_E_INVALID;
+    if (!(cfg->max_step >= 1.0f) || !isfinite(cfg->max_step) || cfg->max_step > 1.0e6f) return BSF_E_INVALID;
+    if (cfg->frac_bits < -1 || cfg->frac_bits > 62) return BSF_E_INVALID;
+    if (H < 0 || W < 0 || H > (int64_t(1) << 31) || W > (int64_t(1) << 31)) return BSF_E_INVALID;
+    int n_up = 0;
+    for (int k = 0; k < cfg->n_dirs; ++k) {
+        const int dx = cfg->dirs[2 * k], dy = cfg->dirs[2 * k + 1];
+        if (dx == 0 && dy == 0) return BSF_E_INVALID;
+        if (gcd_int(dx, dy) != 1) return BSF_E_INVALID;              // primitive
+        if (dx < 0 || (dx == 0 && dy < 0)) return BSF_E_INVALID;     // canonical sign
+        if (dx > 64 || dy > 64 || dy < -64) return BSF_E_INVALID;
+        if (dy < 0) {
+            ++n_up;
+            if (k != cfg->n_dirs - 1) return BSF_E_INVALID;          // only the last pass may be truncated
+        }
+        p->dx[k] = dx;
+        p->dy[k] = dy;
+    }
+    if (n_up > 1) return BSF_E_INVALID;
+    p->n_dirs = cfg->n_dirs;
+    p->order = cfg->order;
+    p->M = cfg->n_dirs * cfg->order;
+    p->tied = cfg->tied ? 1 : 0;
+    p->mode = cfg->mode;
+    p->arith = cfg->arith;
+    p->planes = p->tied ? p->n_dirs : p->M;
+    p->max_step = cfg->max_step;
+    p->R_max = (int)floorf((cfg->max_step - 1.0f) * 0.5f);
+    p->H = H;
+    p->W = W;
+    // Every tap of factor j lies at m u_j with m in [-(R+2), R+1] (both step
+    // modes), so direction k reaches [-r(R+2), r(R+1)] lattice steps.
+    const int64_t lo = (int64_t)p->order * (p->R_max + 2), hi = (int64_t)p->order * (p->R_max + 1);
+    int64_t left = 0, right = 0, top = 0, bottom = 0;
+    for (int k = 0; k < p->n_dirs; ++k) {
+        const int64_t dx = p->dx[k], dy = p->dy[k];
+        left += lo * dx;
+        right += hi * dx;
+        if (dy > 0) {
+            top += lo * dy;
+            bottom += hi * dy;
+        } else {
+            top += hi * (-dy);
+            bottom += lo * (-dy);
+        }
+    }
+    p->pad_top = top;
+    p->pad_bottom = bottom;
+    p->pad_left = left;
+    int64_t Wp = W + left + right;
+    Wp = (Wp + 15) / 16 * 16;
+    p->pad_right = Wp - W - left;
+    p->Wp = Wp;
+    p->Hp = H + top + bottom;
+    p->g_bytes = (size_t)p->Hp * (size_t)p->Wp * 8;
+    p->scan_aux_bytes = scan_aux_bytes(*p);
+    return BSF_OK;
+}
+
+}  // namespace bsf
+
+using namespace bsf;
+
+namespace {
+
+size_t ws_bytes_for(const Plan &p, bool g_internal) {
+    return kStatusBytes + (g_internal ? align_up(p.g_bytes) : 0) + p.scan_aux_bytes;
+}
+
+GatherArgs gather_args(const Plan &p, const void *G, const float *steps, float *out, int64_t *num, int64_t *den,
+                       const int32_t *status) {
+    GatherArgs a;
+    memset(&a, 0, sizeof(a));
+    a.G = G;
+    a.Wp = p.Wp;
+    a.pad_top = p.pad_top;
+    a.pad_left = p.pad_left;
+    a.H = p.H;
+    a.W = p.W;
+    a.steps = steps;
+    a.out = out;
+    a.out_num = num;
+    a.out_den = den;
+    a.status = status;
+    a.max_step = p.max_step;
+    a.M = p.M;
+    a.order = p.order;
+    a.tied = p.tied;
+    a.n_dirs = p.n_dirs;
+    // Factor order: directions in config order, except that for the tied
+    // four-direction order-2 kernel a direction with window offset +1 goes last,
+    // so its taps are contiguous.  The result does not depend on the order.
+    int perm[BSF_MAX_DIRS];
+    for (int k = 0; k < p.n_dirs; ++k) perm[k] = k;
+    if (p.n_dirs == 4 && p.order == 2 && p.tied) {
+        for (int k = 0; k < p.n_dirs; ++k)
+            if (p.dx[k] == 1 && p.dy[k] == 0) {
+                perm[k] = perm[3];
+                perm[3] = k;
+                break;
+            }
+    }
+    for (int kk = 0; kk < p.n_dirs; ++kk) {
+        const int k = perm[kk];
+        for (int q = 0; q < p.order; ++q) {
+            const int j = kk * p.order + q;
+            a.off[j] = (int32_t)(p.dy[k] * p.Wp + p.dx[k]);
+            a.plane[j] = p.tied ? k : k * p.order + q;
+        }
+    }
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+bsf_status bsf_workspace_init(void *ws, size_t ws_bytes, void *stream) {
+    if (!ws || ws_bytes < kStatusBytes) return BSF_E_WORKSPACE;
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                       static_cast<int32_t *>(ws));
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
+}
+
+bsf_status bsf_plan(const bsf_config *cfg, int64_t H, int64_t W, bsf_geometry *geo) {
+    if (!geo) return BSF_E_INVALID;
+    Plan p;
+    bsf_status r = make_plan(cfg, H, W, &p);
+    if (r != BSF_OK) return r;
+    geo->pad_top = p.pad_top;
+    geo->pad_bottom = p.pad_bottom;
+    geo->pad_left = p.pad_left;
+    geo->pad_right = p.pad_right;
+    geo->win_h = p.Hp;
+    geo->win_w = p.Wp;
+    geo->g_bytes = p.g_bytes;
+    geo->workspace_bytes = ws_bytes_for(p, true);
+    geo->workspace_bytes_g_external = ws_bytes_for(p, false);
+    return BSF_OK;
+}
+
+bsf_status bsf_preintegrate(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
+                            int64_t pitch, int32_t F, void *G, void *ws, size_t ws_bytes, void *stream) {
+    Plan p;
+    bsf_status r = make_plan(cfg, H, W, &p);
+    if (r != BSF_OK) return r;
+    const int kind = src_kind_of(dtype);
+    if (kind < 0) return BSF_E_INVALID;
+    if (pitch < W || !G || !ws || (H * W > 0 && !img)) return BSF_E_INVALID;
+    if (F < 0 || F > 62) return BSF_E_INVALID;
+    if (ws_bytes < ws_bytes_for(p, false)) return BSF_E_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int32_t *status = static_cast<int32_t *>(ws);
+    void *aux = static_cast<char *>(ws) + kStatusBytes;
+    hipLaunchKernelGGL(k_set_F, dim3(1), dim3(64), 0, st, status, kind == SRC_F32 ? F : 0);
+    BSF_HIP_CHECK(hipGetLastError());
+    Src src{img, kind, H, W, pitch, p.pad_top, p.pad_left};
+    return run_preintegrate(p, src, G, aux, status, st);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace layout: [status 256 B][G when internal][scan carries].
+struct WsLayout {
+    int32_t *status;
+    void *G;
+    void *aux;
+};
+
+WsLayout ws_layout(const Plan &p, void *ws, void *G_ext) {
+    WsLayout L;
+    char *wsp = static_cast<char *>(ws);
+    L.status = reinterpret_cast<int32_t *>(wsp);
+    wsp += kStatusBytes;
+    L.G = G_ext;
+    if (!L.G) {
+        L.G = wsp;
+        wsp += align_up(p.g_bytes);
+    }
+    L.aux = wsp;
+    return L;
+}
+
+bsf_status prepare_impl(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
+                        int64_t pitch, const float *steps, void *G_ext, void *ws, size_t ws_bytes, void *stream,
+                        Plan &p, WsLayout &L) {
+    bsf_status r = make_plan(cfg, H, W, &p);
+    if (r != BSF_OK) return r;
+    const int kind = src_kind_of(dtype);
+    if (kind < 0) return BSF_E_INVALID;
+    if (pitch < W || !ws) return BSF_E_INVALID;
+    if (H * W > 0 && (!img || !steps)) return BSF_E_INVALID;
+    if (ws_bytes < ws_bytes_for(p, G_ext == nullptr)) return BSF_E_WORKSPACE;
+    L = ws_layout(p, ws, G_ext);
+    if (H * W == 0) return BSF_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Src src{img, kind, H, W, pitch, p.pad_top, p.pad_left};
+    r = run_bound(p, src, steps, kind == SRC_F32 ? cfg->frac_bits : 0, L.status, st, false);
+    if (r != BSF_OK) return r;
+    return run_preintegrate(p, src, L.G, L.aux, L.status, st);
+}
+
+bsf_status apply_checks(const Plan &p, bsf_dtype dtype, int64_t *out_num, int64_t *out_den) {
+    if (src_kind_of(dtype) < 0) return BSF_E_INVALID;
+    if (out_num && (p.mode != BSF_STEPS_INT || p.arith != BSF_ARITH_EXACT)) return BSF_E_INVALID;
+    if (out_den && p.mode != BSF_STEPS_INT) return BSF_E_INVALID;
+    return BSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bsf_status bsf_forward_prepare(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
+                               int64_t pitch, const float *steps, void *G, void *ws, size_t ws_bytes,
+                               void *stream) {
+    Plan p;
+    WsLayout L;
+    return prepare_impl(cfg, dtype, img, H, W, pitch, steps, G, ws, ws_bytes, stream, p, L);
+}
+
+bsf_status bsf_forward_apply(const bsf_config *cfg, bsf_dtype dtype, int64_t H, int64_t W, const float *steps,
+                             const void *G, float *out, int64_t *out_num, int64_t *out_den, void *ws,
+                             size_t ws_bytes, void *stream) {
+    Plan p;
+    bsf_status r = make_plan(cfg, H, W, &p);
+    if (r != BSF_OK) return r;
+    r = apply_checks(p, dtype, out_num, out_den);
+    if (r != BSF_OK) return r;
+    if (!ws || (H * W > 0 && !steps)) return BSF_E_INVALID;
+    if (ws_bytes < ws_bytes_for(p, G == nullptr)) return BSF_E_WORKSPACE;
+    WsLayout L = ws_layout(p, ws, const_cast<void *>(G));
+    if (H * W == 0) return BSF_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Src none{};
+    none.kind = src_kind_of(dtype);
+    r = run_bound(p, none, steps, 0, L.status, st, true);
+    if (r != BSF_OK) return r;
+    GatherArgs a = gather_args(p, L.G, steps, out, out_num, out_den, L.status);
+    return run_gather(p, a, st);
+}
+
+bsf_status bsf_filter_varying(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
+                              int64_t pitch, const float *steps, float *out, int64_t *out_num, int64_t *out_den,
+                              void *G_save, void *ws, size_t ws_bytes, void *stream) {
+    Plan p;
+    bsf_status r = make_plan(cfg, H, W, &p);
+    if (r != BSF_OK) return r;
+    r = apply_checks(p, dtype, out_num, out_den);
+    if (r != BSF_OK) return r;
+    WsLayout L;
+    r = prepare_impl(cfg, dtype, img, H, W, pitch, steps, G_save, ws, ws_bytes, stream, p, L);
+    if (r != BSF_OK || H * W == 0) return r;
+    GatherArgs a = gather_args(p, L.G, steps, out, out_num, out_den, L.status);
+    return run_gather(p, a, static_cast<hipStream_t>(stream));
+}
+
+size_t bsf_backward_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W) {
+    (void)cfg;
+    (void)H;
+    (void)W;
+    return 0;
+}
+
+bsf_status bsf_filter_backward(const bsf_config *cfg, const float *img, int64_t H, int64_t W, int64_t pitch,
+                               const float *steps, const float *gout, float *grad_img, float *grad_steps,
+                               const void *G_saved, void *ws, size_t ws_bytes, void *stream) {
+    (void)cfg; (void)img; (void)H; (void)W; (void)pitch; (void)steps; (void)gout; (void)grad_img;
+    (void)grad_steps; (void)G_saved; (void)ws; (void)ws_bytes; (void)stream;
+    return BSF_E_UNSUPPORTED;
+}
+
+size_t bsf_batched_workspace_bytes(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs) {
+    (void)cfg;
+    (void)B;
+    (void)descs;
+    return 0;
+}
+
+bsf_status bsf_filter_batched(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs, void *ws,
+                              size_t ws_bytes, void *stream, int32_t use_graph) {
+    (void)cfg; (void)B; (void)descs; (void)ws; (void)ws_bytes; (void)stream; (void)use_graph;
+    return BSF_E_UNSUPPORTED;
+}
+
+bsf_status bsf_read_device_status(void *ws, void *stream, uint32_t *flags, int32_t *F_used, int32_t *log2_bound,
+                                  int32_t clear) {
+    if (!ws) return BSF_E_INVALID;
+    BSF_HIP_CHECK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    int32_t h[ST_WORDS];
+    BSF_HIP_CHECK(hipMemcpy(h, ws, sizeof(int32_t) * 8, hipMemcpyDeviceToHost));
+    if (flags) *flags = (uint32_t)h[ST_FLAGS];
+    if (F_used) *F_used = h[ST_F_USED];
+    if (log2_bound) *log2_bound = h[ST_LOG2_BOUND];
+    if (clear) {
+        int32_t z = 0;
+        BSF_HIP_CHECK(hipMemcpy(ws, &z, sizeof(z), hipMemcpyHostToDevice));
+    }
+    return BSF_OK;
+}
+
+const char *bsf_status_string(bsf_status s) {
+    switch (s) {
+    case BSF_OK: return "ok";
+    case BSF_E_INVALID: return "invalid argument";
+    case BSF_E_RANGE: return "step out of range";
+    case BSF_E_OVERFLOW: return "fixed-point overflow";
+    case BSF_E_WORKSPACE: return "workspace too small";
+    case BSF_E_DEVICE: return "device error";
+    case BSF_E_UNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char *bsf_version(void) { return "bsf 0.1 gfx950"; }
+
+}  // extern "C"

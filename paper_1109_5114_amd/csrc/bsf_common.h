@@ -1,0 +1,106 @@
+// Internal definitions shared by the libbsf translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bsf.h"
+
+namespace bsf {
+
+// Status block at the start of every workspace (32-bit words).
+enum StatusWord : int {
+    ST_FLAGS = 0,      // sticky BSF_FLAG_* bits
+    ST_F_USED = 1,     // fixed-point bits used by the last forward pass
+    ST_LOG2_BOUND = 2, // ceil(log2 max|f_q| bound exponent) the choice came from
+    ST_EP_MAX = 3,     // scratch: max over pixels of ceil(log2 prod of box lengths)
+    ST_FABS_BITS = 4,  // scratch: float bits of max |f|
+    ST_F_REQUEST = 5,  // requested F (-1 = auto)
+    ST_EF = 6,         // ceil(log2 max|f|) of the image the window was built from
+    ST_ARITH = 7,      // arithmetic of the window (bsf_arith)
+    ST_WORDS = 64
+};
+constexpr size_t kStatusBytes = 256;
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// Input kinds for the first running-sum pass.
+enum SrcKind : int { SRC_WINDOW = 0, SRC_F32 = 1, SRC_U8 = 2, SRC_U16 = 3 };
+
+// Host-side plan of one (config, H, W).
+struct Plan {
+    int n_dirs, order, M, tied, mode, arith, planes;
+    int dx[BSF_MAX_DIRS], dy[BSF_MAX_DIRS];
+    float max_step;
+    int R_max;                  // floor((max_step - 1) / 2)
+    int64_t H, W;
+    int64_t pad_top, pad_bottom, pad_left, pad_right, Hp, Wp;
+    size_t g_bytes;
+    size_t scan_aux_bytes;      // carries of the line scans
+};
+
+// Source image description for the first pass.
+struct Src {
+    const void *img;
+    int kind;          // SrcKind
+    int64_t H, W, pitch;
+    int64_t pad_top, pad_left;
+};
+
+bsf_status make_plan(const bsf_config *cfg, int64_t H, int64_t W, Plan *p);
+
+// Running sums on the window (scan.hip).  G is int64 (exact) or double (fp64).
+size_t scan_aux_bytes(const Plan &p);
+bsf_status run_preintegrate(const Plan &p, const Src &src, void *G, void *aux, const int32_t *status,
+                            hipStream_t st);
+// Reverse (transposed) running sums on the window, last direction first.
+bsf_status run_preintegrate_transpose(const Plan &p, void *G, void *aux, hipStream_t st);
+
+// Per-pixel taps (gather.hip).
+struct GatherArgs {
+    const void *G;
+    int64_t Wp, pad_top, pad_left;
+    int64_t H, W;
+    const float *steps;     // [planes][H][W]
+    float *out;             // nullable
+    int64_t *out_num;       // nullable
+    int64_t *out_den;       // nullable
+    const int32_t *status;  // F at status[ST_F_USED]
+    float max_step;
+    int M, order, tied, n_dirs;
+    int32_t off[BSF_MAX_FACTORS];    // window offset (elements) of one lattice step along factor j
+    int32_t plane[BSF_MAX_FACTORS];  // step plane of factor j
+};
+bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st);
+
+// Bound / range check and fixed-point choice (gather.hip).
+// prepare: range check, bound and choice of F (recheck = false); apply with
+// possibly different steps: range check and bound against the stored F.
+bsf_status run_bound(const Plan &p, const Src &src, const float *steps, int32_t F_request, int32_t *status,
+                     hipStream_t st, bool recheck);
+
+// Adjoint (adjoint.hip).
+struct AdjointArgs {
+    const void *G;          // forward running sums (int64) for the step gradient
+    void *Ghat;             // int64 window accumulating the scattered stencils
+    int64_t Wp, pad_top, pad_left;
+    int64_t H, W;
+    const float *steps;
+    const float *gout;
+    float *grad_steps;      // nullable
+    const int32_t *status;  // F at status[ST_F_USED]
+    int32_t *gstatus;       // fixed-point bits of the adjoint scatter at [0]
+    float max_step;
+    int M, order, tied, n_dirs;
+    int32_t off[BSF_MAX_FACTORS];
+    int32_t plane[BSF_MAX_FACTORS];
+};
+
+}  // namespace bsf
+
+#define BSF_HIP_CHECK(expr)                                   \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return BSF_E_DEVICE;            \
+    } while (0)

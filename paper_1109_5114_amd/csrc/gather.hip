@@ -1,0 +1,649 @@
+// Per-pixel signed taps of the running sum (Section 1.1, second step of
+// BoxFilter; Table 1; Alg. 3 step 3), plus the range check and the choice of
+// the fixed-point bits.
+//
+// Each box factor j of step s contributes, for integer steps, the difference
+// T_{c} - T_{c-s} of the running sum along u_j (c = floor((s-1)/2)), and for
+// continuous steps the running sum read linearly between lattice points:
+//     D_j = (1 - phi) (T_R - T_{-R-1}) + phi (T_{R+1} - T_{-R-2}),
+//     R = floor((s-1)/2), phi = (s-1)/2 - R,
+// a mix of two odd integer boxes.  The product of the D_j over the M factors is
+// expanded into integer tap combinations J (one per choice of box per factor),
+// each exact modulo 2^64 and small in magnitude, and only then weighted by the
+// FP64 phase products.
+//
+// Pixel mapping: a 256-thread workgroup covers a 16x16 pixel tile and each
+// wavefront an 8x8 block, so the 64 lanes of one tap read an 8x8 (plus step
+// variation) patch of the window, which stays within a few cache lines per row.
+#include <stdlib.h>
+
+#include <type_traits>
+
+#include "bsf_common.h"
+
+namespace bsf {
+namespace {
+
+constexpr int kTile = 16;
+
+__device__ __forceinline__ bool pixel_of_thread(int64_t H, int64_t W, int64_t &x, int64_t &y) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    x = (int64_t)blockIdx.x * kTile + (w & 1) * 8 + (lane & 7);
+    y = (int64_t)blockIdx.y * kTile + (w >> 1) * 8 + (lane >> 3);
+    return x < W && y < H;
+}
+
+__device__ __forceinline__ float clamp_step(float s, float max_step) {
+    // NaN -> 1 (fmaxf returns the non-NaN operand); keeps every tap in the window
+    return fminf(fmaxf(s, 1.0f), max_step);
+}
+
+__device__ __forceinline__ double ldexp_neg(double v, int F) { return __builtin_ldexp(v, -F); }
+
+// ----------------------------------------------------------------------------
+// Range check and fixed-point bound.
+// ----------------------------------------------------------------------------
+__global__ void k_status_begin(int32_t *status, int32_t F_request, int recheck) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        status[ST_EP_MAX] = 0;
+        if (!recheck) {
+            status[ST_FABS_BITS] = 0;
+            status[ST_F_REQUEST] = F_request;
+        }
+    }
+}
+
+// ceil(log2(v)) for v >= 1, from the binary exponent (frexp: v = m 2^e, m in [0.5, 1)).
+__device__ __forceinline__ int ceil_log2(double v) {
+    int e;
+    const double m = __builtin_frexp(v, &e);
+    return m == 0.5 ? e - 1 : e;
+}
+
+// One workgroup per group of rows (grid-stride over rows, threads stride over
+// columns), a wavefront and LDS reduction, and one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_bound(const float *__restrict__ steps, int64_t H, int64_t W, int planes,
+                                               int per_plane, int mode, float max_step,
+                                               const float *__restrict__ img, int64_t pitch, int32_t *status) {
+    __shared__ int s_ep[4], s_bad[4];
+    __shared__ unsigned s_fb[4];
+    int ep_max = 0;
+    unsigned fbits = 0;
+    int bad = 0;
+    const int64_t HW = H * W;
+    for (int64_t y = blockIdx.x; y < H; y += gridDim.x) {
+        for (int64_t x = threadIdx.x; x < W; x += blockDim.x) {
+            const int64_t i = y * W + x;
+            double prod = 1.0;
+            for (int q = 0; q < planes; ++q) {
+                const float s = steps[q * HW + i];
+                if (!(s >= 1.0f) || s > max_step) bad = 1;  // catches NaN
+                const float sc = clamp_step(s, max_step);
+                double len;
+                if (mode == BSF_STEPS_INT) {
+                    if (sc != floorf(sc)) bad = 1;
+                    len = (double)rintf(sc);
+                } else {
+                    len = (double)(2.0f * floorf((sc - 1.0f) * 0.5f) + 3.0f);
+                }
+                for (int r = 0; r < per_plane; ++r) prod *= len;
+            }
+            // products of small integers are exact in FP64 up to 2^53; above
+            // that round the bound up a little so it stays an upper bound
+            ep_max = max(ep_max, ceil_log2(prod * (1.0 + 0x1p-40)));
+            if (img) {
+                const float f = fabsf(img[y * pitch + x]);
+                if (f == f) fbits = max(fbits, __float_as_uint(f));
+            }
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        ep_max = max(ep_max, __shfl_xor(ep_max, d, 64));
+        fbits = max(fbits, (unsigned)__shfl_xor((int)fbits, d, 64));
+        bad |= __shfl_xor(bad, d, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_ep[w] = ep_max;
+        s_fb[w] = fbits;
+        s_bad[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            ep_max = max(ep_max, s_ep[k]);
+            fbits = max(fbits, s_fb[k]);
+            bad |= s_bad[k];
+        }
+        atomicMax(&status[ST_EP_MAX], ep_max);
+        if (img) atomicMax((unsigned *)&status[ST_FABS_BITS], fbits);
+        if (bad) atomicOr((unsigned *)&status[ST_FLAGS], BSF_FLAG_RANGE);
+    }
+}
+
+// img_kind: SRC_F32, SRC_U8 or SRC_U16; arith: exact or fp64.
+__global__ void k_choose_F(int32_t *status, int img_kind, int arith) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int eP = status[ST_EP_MAX];
+    int ef;
+    bool zero = false;
+    if (img_kind == SRC_U8) {
+        ef = 8;
+    } else if (img_kind == SRC_U16) {
+        ef = 16;
+    } else {
+        const float fmax = __uint_as_float((unsigned)status[ST_FABS_BITS]);
+        if (fmax == 0.0f) {
+            zero = true;
+            ef = 0;
+        } else {
+            ef = ceil_log2((double)fmax);  // |f| <= 2^ef
+        }
+    }
+    int F;
+    if (img_kind != SRC_F32) {
+        F = 0;
+    } else if (status[ST_F_REQUEST] >= 0) {
+        F = status[ST_F_REQUEST];
+    } else {
+        F = 62 - (zero ? 0 : ef) - eP;
+        if (F > 62) F = 62;
+        if (F < 0) F = 0;
+    }
+    // |f_q| <= 2^(ef + F) (+1/2 from rounding) and |J| <= |f_q| * prod <= 2^(ef + F + eP)
+    if (arith == BSF_ARITH_EXACT && !zero && ef + F + eP > 62)
+        atomicOr((unsigned *)&status[ST_FLAGS], BSF_FLAG_OVERFLOW);
+    status[ST_F_USED] = F;
+    status[ST_LOG2_BOUND] = ef + eP;
+    status[ST_EF] = zero ? -1000 : ef;
+    status[ST_ARITH] = arith;
+}
+
+// New steps on an existing window: the stored F and image bound must still
+// hold for the new step products.
+__global__ void k_check_F(int32_t *status) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int eP = status[ST_EP_MAX], ef = status[ST_EF], F = status[ST_F_USED];
+    if (status[ST_ARITH] == BSF_ARITH_EXACT && ef > -1000 && ef + F + eP > 62)
+        atomicOr((unsigned *)&status[ST_FLAGS], BSF_FLAG_OVERFLOW);
+    if (ef > -1000 && ef + eP > status[ST_LOG2_BOUND]) status[ST_LOG2_BOUND] = ef + eP;
+}
+
+// ----------------------------------------------------------------------------
+// Integer steps: 2^M signed taps (Table 1 signs (-1)^popcount), exact.
+// ----------------------------------------------------------------------------
+template <typename V, int MT>
+__global__ __launch_bounds__(256) void k_gather_int(GatherArgs a) {
+    int64_t x, y;
+    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    const int M = MT > 0 ? MT : a.M;
+    const int64_t HW = a.H * a.W, idx = y * a.W + x;
+    const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
+    int64_t pa[BSF_MAX_FACTORS], pb[BSF_MAX_FACTORS];
+    int64_t den = 1;
+#pragma unroll
+    for (int j = 0; j < (MT > 0 ? MT : BSF_MAX_FACTORS); ++j) {
+        if (j >= M) break;
+        const float s = clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
+        const int si = min((int)rintf(s), (int)a.max_step);   // stays inside the window's reach
+        const int c = (si - 1) >> 1;
+        pa[j] = (int64_t)c * a.off[j];
+        pb[j] = (int64_t)(c - si) * a.off[j];
+        den *= si;
+    }
+    V num = V(0);
+    const int n = 1 << M;
+    if constexpr (MT > 0) {
+#pragma unroll
+        for (int e = 0; e < (1 << MT); ++e) {
+            int64_t o = 0;
+#pragma unroll
+            for (int j = 0; j < MT; ++j) o += (e >> j & 1) ? pb[j] : pa[j];
+            if (__builtin_popcount(e) & 1) num -= G[o];
+            else num += G[o];
+        }
+    } else {
+        for (int e = 0; e < n; ++e) {
+            int64_t o = 0;
+            for (int j = 0; j < M; ++j) o += (e >> j & 1) ? pb[j] : pa[j];
+            if (__builtin_popcount(e) & 1) num -= G[o];
+            else num += G[o];
+        }
+    }
+    if constexpr (std::is_integral_v<V>) {
+        const int F = a.status[ST_F_USED];
+        if (a.out_num) a.out_num[idx] = num;
+        if (a.out_den) a.out_den[idx] = den;
+        if (a.out) a.out[idx] = (float)(ldexp_neg((double)num, F) / (double)den);
+    } else {
+        if (a.out_den) a.out_den[idx] = den;
+        if (a.out) a.out[idx] = (float)(num / (double)den);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Continuous steps, any factor count: per factor two integer boxes; 2^M box
+// choices e, each an exact 2^M-tap combination J_e, weighted by
+// prod_j (e_j ? phi_j : 1 - phi_j).  4^M loads per pixel: the reference path
+// for configurations without a specialised kernel.
+// ----------------------------------------------------------------------------
+template <typename V>
+__global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs a) {
+    int64_t x, y;
+    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    const int M = a.M;
+    const int64_t HW = a.H * a.W, idx = y * a.W + x;
+    const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
+    int64_t pos[BSF_MAX_FACTORS][4];  // [j][2*e + t]: e = box (0 narrow, 1 wide), t = end (0 top, 1 bottom)
+    double ph[BSF_MAX_FACTORS];
+    double den = 1.0;
+    for (int j = 0; j < M; ++j) {
+        const float s = clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
+        const float t = (s - 1.0f) * 0.5f;
+        const float R = floorf(t);
+        ph[j] = (double)(t - R);
+        const int64_t Ri = (int64_t)R;
+        pos[j][0] = Ri * a.off[j];
+        pos[j][1] = (-Ri - 1) * a.off[j];
+        pos[j][2] = (Ri + 1) * a.off[j];
+        pos[j][3] = (-Ri - 2) * a.off[j];
+        den *= (double)s;
+    }
+    double tot = 0.0;
+    const int n = 1 << M;
+    for (int e = 0; e < n; ++e) {
+        double w = 1.0;
+        for (int j = 0; j < M; ++j) w *= (e >> j & 1) ? ph[j] : 1.0 - ph[j];
+        if (w == 0.0) continue;
+        V J = V(0);
+        for (int t = 0; t < n; ++t) {
+            int64_t o = 0;
+            for (int j = 0; j < M; ++j) o += pos[j][2 * (e >> j & 1) + (t >> j & 1)];
+            if (__builtin_popcount(t) & 1) J -= G[o];
+            else J += G[o];
+        }
+        tot += w * (double)J;
+    }
+    if constexpr (std::is_integral_v<V>) {
+        const int F = a.status[ST_F_USED];
+        if (a.out) a.out[idx] = (float)(ldexp_neg(tot, F) / den);
+    } else {
+        if (a.out) a.out[idx] = (float)(tot / den);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Continuous steps, four directions, order 2, steps tied per direction.
+//
+// Per direction k the squared difference D_k^2 =
+//   (1-phi)^2 P_a^2 + 2 phi (1-phi) P_a P_b + phi^2 P_b^2
+// touches 9 lattice positions in three clusters of three consecutive points,
+//   T = 2R + {0,1,2},  M = -2 + {0,1,2},  B = -2R - 4 + {0,1,2},
+// and the three integer operators read them as
+//   aa = P_a^2    = T0 - 2 M1 + B2
+//   ab = P_a P_b  = T1 - M0 - M2 + B1
+//   bb = P_b^2    = T2 - 2 M1 + B0.
+// The 3^4 = 81 products J[a0][a1][a2][a3] are contracted one direction at a
+// time (innermost first) in exact int64; the innermost direction is the one
+// with window offset +1 when the set has it, so each cluster is three
+// consecutive int64.  The outermost direction's taps are visited in an order
+// that finishes one operator at a time, so only 27 accumulators are live.
+// ----------------------------------------------------------------------------
+
+// Tap index -> (operator, coefficient) memberships, index order
+// T0 T1 T2 M0 M1 M2 B0 B1 B2.
+__device__ __forceinline__ void offsets9(int32_t R, int32_t off, int32_t o[9]) {
+    const int32_t t = 2 * R * off, m = -2 * off, b = (-2 * R - 4) * off;
+    o[0] = t; o[1] = t + off; o[2] = t + 2 * off;
+    o[3] = m; o[4] = m + off; o[5] = m + 2 * off;
+    o[6] = b; o[7] = b + off; o[8] = b + 2 * off;
+}
+
+// acc[a1][a2][a3] += sum_{p1,p2,p3} C1 C2 C3 G[b + o1[p1] + o2[p2] + o3[p3]]
+// (directions 1..3 of the contraction; direction 3 innermost).
+// Offsets are 32-bit element indices into the window (the launcher checks the
+// window has fewer than 2^31 elements), so every load is base + 32-bit offset.
+__device__ __forceinline__ void contract3(const int64_t *__restrict__ G, int32_t b, const int32_t o1[9],
+                                          const int32_t o2[9], const int32_t o3[9], int64_t acc[27]) {
+#pragma unroll
+    for (int p1 = 0; p1 < 9; ++p1) {
+        int64_t ipos[9], ineg[9];  // [a2][a3]
+#pragma unroll
+        for (int i = 0; i < 9; ++i) { ipos[i] = 0; ineg[i] = 0; }
+#pragma unroll
+        for (int p2 = 0; p2 < 9; ++p2) {
+            const int32_t bb = b + o1[p1] + o2[p2];
+            int64_t v[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[i] = G[(uint32_t)(bb + o3[i])];
+            const int64_t m2 = v[4] * 2;
+            int64_t s[3];
+            s[0] = v[0] + v[8] - m2;          // aa
+            s[1] = v[1] + v[7] - v[3] - v[5]; // ab
+            s[2] = v[2] + v[6] - m2;          // bb
+            // fold direction 2 (tap p2) into [a2][a3]
+            if (p2 == 0 || p2 == 8) { for (int i = 0; i < 3; ++i) ipos[0 * 3 + i] += s[i]; }
+            if (p2 == 1 || p2 == 7) { for (int i = 0; i < 3; ++i) ipos[1 * 3 + i] += s[i]; }
+            if (p2 == 2 || p2 == 6) { for (int i = 0; i < 3; ++i) ipos[2 * 3 + i] += s[i]; }
+            if (p2 == 3 || p2 == 5) { for (int i = 0; i < 3; ++i) ineg[1 * 3 + i] += s[i]; }
+            if (p2 == 4) {
+                for (int i = 0; i < 3; ++i) {
+                    ineg[0 * 3 + i] += 2 * s[i];
+                    ineg[2 * 3 + i] += 2 * s[i];
+                }
+            }
+        }
+        // fold direction 1 (tap p1) into acc[a1][a2][a3]
+        const bool neg = (p1 >= 3 && p1 <= 5);
+        int64_t in[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) in[i] = neg ? ineg[i] - ipos[i] : ipos[i] - ineg[i];
+        if (p1 == 0 || p1 == 8) { for (int i = 0; i < 9; ++i) acc[0 * 9 + i] += in[i]; }
+        if (p1 == 1 || p1 == 7) { for (int i = 0; i < 9; ++i) acc[1 * 9 + i] += in[i]; }
+        if (p1 == 2 || p1 == 6) { for (int i = 0; i < 9; ++i) acc[2 * 9 + i] += in[i]; }
+        if (p1 == 3 || p1 == 5) { for (int i = 0; i < 9; ++i) acc[1 * 9 + i] += in[i]; }
+        if (p1 == 4) {
+            for (int i = 0; i < 9; ++i) {
+                acc[0 * 9 + i] += 2 * in[i];
+                acc[2 * 9 + i] += 2 * in[i];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double contract_fp(const int64_t acc[27], const double w1[3], const double w2[3],
+                                              const double w3[3]) {
+    double r = 0.0;
+#pragma unroll
+    for (int a1 = 0; a1 < 3; ++a1) {
+        double r1 = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int a3 = 0; a3 < 3; ++a3) r2 += w3[a3] * (double)acc[(a1 * 3 + a2) * 3 + a3];
+            r1 += w2[a2] * r2;
+        }
+        r += w1[a1] * r1;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_gather_t2n4(GatherArgs a) {
+    int64_t x, y;
+    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    const int64_t HW = a.H * a.W, idx = y * a.W + x;
+    const int64_t *G = static_cast<const int64_t *>(a.G);
+    const int32_t base = (int32_t)((y + a.pad_top) * a.Wp + (x + a.pad_left));
+    // contraction direction k uses config factor 2k (tied: both copies share the plane)
+    int32_t o[4][9];
+    double w[4][3];
+    double den = 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float s = clamp_step(a.steps[a.plane[2 * k] * HW + idx], a.max_step);
+        const float t = (s - 1.0f) * 0.5f;
+        const float Rf = floorf(t);
+        const double ph = (double)(t - Rf);
+        offsets9((int32_t)Rf, a.off[2 * k], o[k]);
+        w[k][0] = (1.0 - ph) * (1.0 - ph);
+        w[k][1] = 2.0 * ph * (1.0 - ph);
+        w[k][2] = ph * ph;
+        den *= (double)s * (double)s;
+    }
+    // direction 0 outermost: visit (tap, action) so one operator finishes at a time
+    //   aa: -2 M1, + T0, + B2;   bb: -2 M1, + T2, + B0;   ab: -(M0 + M2), + T1, + B1
+    constexpr int kSeq[10] = {4, 0, 8, 4, 2, 6, 3, 5, 1, 7};
+    double tot = 0.0;
+    int64_t acc[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) acc[i] = 0;
+    for (int i = 0; i < 10; ++i) {
+        const int p0 = kSeq[i];
+        if (i == 0 || i == 3 || i == 6) {
+#pragma unroll
+            for (int q = 0; q < 27; ++q) acc[q] = 0;
+        }
+        int32_t ob = o[0][0];
+#pragma unroll
+        for (int q = 1; q < 9; ++q) ob = (p0 == q) ? o[0][q] : ob;
+        contract3(G, base + ob, o[1], o[2], o[3], acc);
+        if (i == 0 || i == 3) {
+#pragma unroll
+            for (int q = 0; q < 27; ++q) acc[q] = -2 * acc[q];
+        }
+        if (i == 7) {
+#pragma unroll
+            for (int q = 0; q < 27; ++q) acc[q] = -acc[q];
+        }
+        if (i == 2) tot += w[0][0] * contract_fp(acc, w[1], w[2], w[3]);
+        if (i == 5) tot += w[0][2] * contract_fp(acc, w[1], w[2], w[3]);
+        if (i == 9) tot += w[0][1] * contract_fp(acc, w[1], w[2], w[3]);
+    }
+    const int F = a.status[ST_F_USED];
+    if (a.out) a.out[idx] = (float)(ldexp_neg(tot, F) / den);
+}
+
+// Same contraction, organised to keep few values live: the two outer
+// directions are walked operator pair by operator pair (a0, a1), so only the 9
+// values J[a0][a1][.][.] accumulate; every outer tap pair (t0, t1) forms the
+// 81-tap inner block.  Offsets are 32-bit byte offsets from the window base
+// (window < 4 GiB), the inner block keeps positive and negative parts apart
+// so it only adds, and the sign and power of two of the outer coefficients are
+// applied once per block.  10 x 10 outer tap pairs: 8100 loads per pixel.
+struct Tap {
+    int8_t cluster, sub, coef;  // cluster 0 = T, 1 = M, 2 = B
+};
+__constant__ Tap kOpTaps[3][4] = {
+    {{0, 0, 1}, {1, 1, -2}, {2, 2, 1}, {0, 0, 0}},    // aa
+    {{0, 1, 1}, {1, 0, -1}, {1, 2, -1}, {2, 1, 1}},   // ab
+    {{0, 2, 1}, {1, 1, -2}, {2, 0, 1}, {0, 0, 0}},    // bb
+};
+__constant__ int kOpN[3] = {3, 4, 3};
+
+__device__ __forceinline__ int64_t ld64(const char *__restrict__ Gb, uint32_t byte_off) {
+    return *reinterpret_cast<const int64_t *>(Gb + byte_off);
+}
+
+__global__ __launch_bounds__(256) void k_gather_t2n4_pairs(GatherArgs a) {
+    int64_t x, y;
+    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    const int64_t HW = a.H * a.W, idx = y * a.W + x;
+    const char *Gb = static_cast<const char *>(a.G);
+    const uint32_t base = (uint32_t)(((y + a.pad_top) * a.Wp + (x + a.pad_left)) * 8);
+    int32_t cT[4], cB[4], cM[4], st[4];
+    float ph[4];
+    double den = 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float s = clamp_step(a.steps[a.plane[2 * k] * HW + idx], a.max_step);
+        const float t = (s - 1.0f) * 0.5f;
+        const float Rf = floorf(t);
+        const int32_t R = (int32_t)Rf, off8 = a.off[2 * k] * 8;
+        ph[k] = t - Rf;
+        st[k] = off8;
+        cT[k] = 2 * R * off8;
+        cM[k] = -2 * off8;
+        cB[k] = (-2 * R - 4) * off8;
+        den *= (double)s * (double)s;
+    }
+    double tot = 0.0;
+    for (int a0 = 0; a0 < 3; ++a0) {
+        for (int a1 = 0; a1 < 3; ++a1) {
+            int64_t acc[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) acc[i] = 0;
+            for (int i0 = 0; i0 < kOpN[a0]; ++i0) {
+                const Tap t0 = kOpTaps[a0][i0];
+                const int32_t o0 = (t0.cluster == 0 ? cT[0] : t0.cluster == 1 ? cM[0] : cB[0]) + t0.sub * st[0];
+                for (int i1 = 0; i1 < kOpN[a1]; ++i1) {
+                    const Tap t1 = kOpTaps[a1][i1];
+                    const int32_t o1 =
+                        (t1.cluster == 0 ? cT[1] : t1.cluster == 1 ? cM[1] : cB[1]) + t1.sub * st[1];
+                    const uint32_t b = base + (uint32_t)(o0 + o1);
+                    int64_t ipos[9], ineg[9];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) { ipos[i] = 0; ineg[i] = 0; }
+#pragma unroll
+                    for (int p2 = 0; p2 < 9; ++p2) {
+                        const int c2 = p2 / 3, s2 = p2 % 3;
+                        const uint32_t b2 =
+                            b + (uint32_t)((c2 == 0 ? cT[2] : c2 == 1 ? cM[2] : cB[2]) + s2 * st[2]);
+                        const uint32_t bT = b2 + (uint32_t)cT[3], bM = b2 + (uint32_t)cM[3],
+                                       bB = b2 + (uint32_t)cB[3];
+                        const int64_t T0 = ld64(Gb, bT), T1 = ld64(Gb, bT + st[3]), T2 = ld64(Gb, bT + 2 * st[3]);
+                        const int64_t M0 = ld64(Gb, bM), M1 = ld64(Gb, bM + st[3]), M2 = ld64(Gb, bM + 2 * st[3]);
+                        const int64_t B0 = ld64(Gb, bB), B1 = ld64(Gb, bB + st[3]), B2 = ld64(Gb, bB + 2 * st[3]);
+                        // aa = T0 + B2 - 2 M1, ab = T1 + B1 - (M0 + M2), bb = T2 + B0 - 2 M1
+                        const int64_t P[3] = {T0 + B2, T1 + B1, T2 + B0};
+                        const int64_t m1x2 = M1 * 2;
+                        const int64_t N[3] = {m1x2, M0 + M2, m1x2};
+                        // direction-2 tap p2 = (c2, s2): T/B taps are +1, M taps -1 or -2
+                        if (c2 != 1) {
+                            const int a2 = (c2 == 0) ? s2 : 2 - s2;
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) { ipos[a2 * 3 + i] += P[i]; ineg[a2 * 3 + i] += N[i]; }
+                        } else if (s2 != 1) {
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) { ipos[3 + i] += N[i]; ineg[3 + i] += P[i]; }
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) {
+                                ipos[0 + i] += 2 * N[i]; ineg[0 + i] += 2 * P[i];
+                                ipos[6 + i] += 2 * N[i]; ineg[6 + i] += 2 * P[i];
+                            }
+                        }
+                    }
+                    const int c = t0.coef * t1.coef;   // +-1, +-2 or 4
+                    const int sh = (c == 1 || c == -1) ? 0 : (c == 4 ? 2 : 1);
+                    if (c > 0) {
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) acc[i] += (ipos[i] - ineg[i]) << sh;
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) acc[i] += (ineg[i] - ipos[i]) << sh;
+                    }
+                }
+            }
+            // J[a0][a1][a2][a3] complete: apply the FP64 phase weights
+            const double q2 = 1.0 - ph[2], p2w = ph[2], q3 = 1.0 - ph[3], p3w = ph[3];
+            const double w2[3] = {q2 * q2, 2.0 * p2w * q2, p2w * p2w};
+            const double w3[3] = {q3 * q3, 2.0 * p3w * q3, p3w * p3w};
+            double r = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < 3; ++a2) {
+                double r2 = 0.0;
+#pragma unroll
+                for (int a3 = 0; a3 < 3; ++a3) r2 += w3[a3] * (double)acc[a2 * 3 + a3];
+                r += w2[a2] * r2;
+            }
+            const double p0w = ph[0], q0 = 1.0 - p0w, p1w = ph[1], q1 = 1.0 - p1w;
+            const double w0 = a0 == 0 ? q0 * q0 : a0 == 1 ? 2.0 * p0w * q0 : p0w * p0w;
+            const double w1 = a1 == 0 ? q1 * q1 : a1 == 1 ? 2.0 * p1w * q1 : p1w * p1w;
+            tot += w0 * w1 * r;
+        }
+    }
+    const int F = a.status[ST_F_USED];
+    if (a.out) a.out[idx] = (float)(ldexp_neg(tot, F) / den);
+}
+
+// Plain FP64 counterpart: FP64 running sums and FP64 tap weights
+//   T0:(1-p)^2 T1:2p(1-p) T2:p^2 M0:-2p(1-p) M1:-2((1-p)^2+p^2) M2:-2p(1-p) B0:p^2 B1:2p(1-p) B2:(1-p)^2
+__global__ __launch_bounds__(256) void k_gather_t2n4_fp64(GatherArgs a) {
+    int64_t x, y;
+    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    const int64_t HW = a.H * a.W, idx = y * a.W + x;
+    const double *G = static_cast<const double *>(a.G);
+    const int32_t base = (int32_t)((y + a.pad_top) * a.Wp + (x + a.pad_left));
+    int32_t o[4][9];
+    double w[4][9];
+    double den = 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float s = clamp_step(a.steps[a.plane[2 * k] * HW + idx], a.max_step);
+        const float t = (s - 1.0f) * 0.5f;
+        const float Rf = floorf(t);
+        const double p = (double)(t - Rf), q = 1.0 - p;
+        offsets9((int32_t)Rf, a.off[2 * k], o[k]);
+        w[k][0] = q * q; w[k][1] = 2 * p * q; w[k][2] = p * p;
+        w[k][3] = -2 * p * q; w[k][4] = -2 * (q * q + p * p); w[k][5] = -2 * p * q;
+        w[k][6] = p * p; w[k][7] = 2 * p * q; w[k][8] = q * q;
+        den *= (double)s * (double)s;
+    }
+    double tot = 0.0;
+    for (int p0 = 0; p0 < 9; ++p0) {
+        double t1 = 0.0;
+#pragma unroll
+        for (int p1 = 0; p1 < 9; ++p1) {
+            double t2 = 0.0;
+#pragma unroll
+            for (int p2 = 0; p2 < 9; ++p2) {
+                const int32_t bb = base + o[0][p0] + o[1][p1] + o[2][p2];
+                double t3 = 0.0;
+#pragma unroll
+                for (int p3 = 0; p3 < 9; ++p3) t3 += w[3][p3] * G[(uint32_t)(bb + o[3][p3])];
+                t2 += w[2][p2] * t3;
+            }
+            t1 += w[1][p1] * t2;
+        }
+        tot += w[0][p0] * t1;
+    }
+    if (a.out) a.out[idx] = (float)(tot / den);
+}
+
+// Kernel variant of the tied order-2 four-direction contraction; the tuner
+// (BSF_T2N4_VARIANT) may override the default.
+int t2n4_variant() {
+    static int v = [] {
+        const char *e = getenv("BSF_T2N4_VARIANT");
+        return e ? atoi(e) : 0;
+    }();
+    return v;
+}
+
+}  // namespace
+
+bsf_status run_bound(const Plan &p, const Src &src, const float *steps, int32_t F_request, int32_t *status,
+                     hipStream_t st, bool recheck) {
+    hipLaunchKernelGGL(k_status_begin, dim3(1), dim3(64), 0, st, status, F_request, recheck ? 1 : 0);
+    BSF_HIP_CHECK(hipGetLastError());
+    int64_t blocks = p.H < 2048 ? p.H : 2048;
+    if (blocks < 1) blocks = 1;
+    const float *img = (!recheck && src.kind == SRC_F32) ? static_cast<const float *>(src.img) : nullptr;
+    hipLaunchKernelGGL(k_bound, dim3((unsigned)blocks), dim3(256), 0, st, steps, p.H, p.W, p.planes,
+                       p.tied ? p.order : 1, p.mode, p.max_step, img, src.pitch, status);
+    BSF_HIP_CHECK(hipGetLastError());
+    if (recheck)
+        hipLaunchKernelGGL(k_check_F, dim3(1), dim3(64), 0, st, status);
+    else
+        hipLaunchKernelGGL(k_choose_F, dim3(1), dim3(64), 0, st, status, src.kind, p.arith);
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
+}
+
+bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st) {
+    if (p.H == 0 || p.W == 0) return BSF_OK;
+    dim3 grid((unsigned)((p.W + kTile - 1) / kTile), (unsigned)((p.H + kTile - 1) / kTile));
+    dim3 block(256);
+    const bool fp64 = p.arith == BSF_ARITH_FP64;
+    if (p.mode == BSF_STEPS_INT) {
+        if (p.M == 4) {
+            if (fp64) hipLaunchKernelGGL((k_gather_int<double, 4>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((k_gather_int<int64_t, 4>), grid, block, 0, st, a);
+        } else {
+            if (fp64) hipLaunchKernelGGL((k_gather_int<double, 0>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((k_gather_int<int64_t, 0>), grid, block, 0, st, a);
+        }
+    } else if (p.n_dirs == 4 && p.order == 2 && p.tied && p.Hp * p.Wp < (int64_t(1) << 31)) {
+        if (fp64) hipLaunchKernelGGL(k_gather_t2n4_fp64, grid, block, 0, st, a);
+        else if (t2n4_variant() == 1) hipLaunchKernelGGL(k_gather_t2n4_pairs, grid, block, 0, st, a);
+        else hipLaunchKernelGGL(k_gather_t2n4, grid, block, 0, st, a);
+    } else {
+        if (fp64) hipLaunchKernelGGL((k_gather_real_generic<double>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_gather_real_generic<int64_t>), grid, block, 0, st, a);
+    }
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
+}
+
+}  // namespace bsf

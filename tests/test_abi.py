@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+include/bsf.h declares, and validates arguments before touching a device.
+No compute call runs here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1109_5114_amd as bsf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "bsf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bsf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = bsf.lib()
+    names = header_functions()
+    assert "bsf_filter_varying" in names and "bsf_filter_backward" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(bsf.EXPORTS)
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in bsf.version()
+    for code in range(7):
+        assert bsf.status_string(code)
+
+
+def geo(cfg, H=64, W=80):
+    return bsf.plan(cfg, H, W)
+
+
+def test_plan_window_covers_every_tap():
+    cfg = bsf.Config(order=2, max_step=15.0)
+    g = geo(cfg)
+    R = 7
+    # per direction the taps reach [-r(R+2), r(R+1)] lattice steps
+    assert g.pad_left == 2 * (R + 2) * 3            # three directions with dx = 1
+    assert g.pad_right >= 2 * (R + 1) * 3
+    assert g.pad_top == 2 * (R + 2) * 2 + 2 * (R + 1)   # (0,1), (1,1) down; (1,-1) up
+    assert g.pad_bottom == 2 * (R + 1) * 2 + 2 * (R + 2)
+    assert g.win_w % 16 == 0
+    assert g.win_h == 64 + g.pad_top + g.pad_bottom
+    assert g.g_bytes == g.win_h * g.win_w * 8
+    assert g.workspace_bytes >= g.g_bytes + g.workspace_bytes_g_external
+
+
+@pytest.mark.parametrize("dirs", [
+    ((0, 0),),                      # zero vector
+    ((2, 0),),                      # not primitive
+    ((2, 4), (1, 0)),               # not primitive
+    ((-1, 1),),                     # not canonical sign
+    ((0, -1),),                     # not canonical sign
+    ((1, -1), (1, 0)),              # an upward direction that is not last
+    ((1, -1), (2, -1)),             # two upward directions
+])
+def test_plan_rejects_bad_directions(dirs):
+    with pytest.raises(bsf.BsfError) as e:
+        geo(bsf.Config(dirs=dirs))
+    assert e.value.code == bsf.E_INVALID
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(order=0), bsf.E_INVALID),
+    (dict(order=5), bsf.E_UNSUPPORTED),
+    (dict(order=4, dirs=((1, 0), (0, 1), (1, 1), (1, -1), (2, 1))), bsf.E_INVALID),   # M = 20 > 16
+    (dict(max_step=0.5), bsf.E_INVALID),
+    (dict(max_step=float("nan")), bsf.E_INVALID),
+    (dict(frac_bits=63), bsf.E_INVALID),
+    (dict(mode=7), bsf.E_INVALID),
+    (dict(arith=3), bsf.E_INVALID),
+])
+def test_plan_rejects_bad_config(kw, code):
+    with pytest.raises(bsf.BsfError) as e:
+        geo(bsf.Config(**kw))
+    assert e.value.code == code
+
+
+def test_plan_rejects_bad_sizes():
+    with pytest.raises(bsf.BsfError):
+        bsf.plan(bsf.Config(), -1, 5)
+    g = bsf.plan(bsf.Config(), 0, 0)     # empty image is valid
+    assert g.win_h == g.pad_top + g.pad_bottom
+
+
+def test_entry_points_validate_before_launch():
+    """Argument errors return before anything is enqueued (null pointers are
+    never dereferenced, so this runs without a device)."""
+    L = bsf.lib()
+    cfg = bsf.Config().c()
+    NULL = None
+    # pitch < W
+    r = L.bsf_filter_varying(ctypes.byref(cfg), bsf.F32, ctypes.c_void_p(16), 8, 8, 4, ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), NULL, NULL, NULL, ctypes.c_void_p(16), 1 << 30, NULL)
+    assert r == bsf.E_INVALID
+    # workspace too small
+    r = L.bsf_filter_varying(ctypes.byref(cfg), bsf.F32, ctypes.c_void_p(16), 8, 8, 8, ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), NULL, NULL, NULL, ctypes.c_void_p(16), 16, NULL)
+    assert r == bsf.E_WORKSPACE
+    # bad dtype
+    r = L.bsf_filter_varying(ctypes.byref(cfg), 9, ctypes.c_void_p(16), 8, 8, 8, ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), NULL, NULL, NULL, ctypes.c_void_p(16), 1 << 30, NULL)
+    assert r == bsf.E_INVALID
+    # numerator output only in integer mode
+    r = L.bsf_filter_varying(ctypes.byref(cfg), bsf.U8, ctypes.c_void_p(16), 8, 8, 8, ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), ctypes.c_void_p(16), NULL, NULL, ctypes.c_void_p(16), 1 << 30,
+                             NULL)
+    assert r == bsf.E_INVALID
+    # preintegrate: F out of range, null G
+    r = L.bsf_preintegrate(ctypes.byref(cfg), bsf.F32, ctypes.c_void_p(16), 8, 8, 8, 63, ctypes.c_void_p(16),
+                           ctypes.c_void_p(16), 1 << 30, NULL)
+    assert r == bsf.E_INVALID
+    r = L.bsf_preintegrate(ctypes.byref(cfg), bsf.F32, ctypes.c_void_p(16), 8, 8, 8, 24, NULL,
+                           ctypes.c_void_p(16), 1 << 30, NULL)
+    assert r == bsf.E_INVALID
+    r = L.bsf_workspace_init(ctypes.c_void_p(16), 8, NULL)
+    assert r == bsf.E_WORKSPACE

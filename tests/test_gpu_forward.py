@@ -1,0 +1,235 @@
+"""GPU parity of the forward path (pre-integration, taps, normalisation)
+against the CPU oracle, through the C ABI.  Integer work is compared bit for
+bit; FP32 outputs within the bound of gpu_util.float_tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1109_5114_amd as bsf
+import workloads as WL
+from tests.gpu_util import assert_close, cfg_of, note, run_forward
+
+pytestmark = pytest.mark.gpu
+
+DIRS4 = ((1, 0), (0, 1), (1, 1), (1, -1))
+
+
+def sample_pixels(H, W, n, seed):
+    rng = np.random.default_rng(seed)
+    ys = list(rng.integers(0, H, n)) + [0, 0, H - 1, H - 1, H // 2, 0, H - 1]
+    xs = list(rng.integers(0, W, n)) + [0, W - 1, 0, W - 1, W // 2, W // 2, W // 3]
+    return np.array(ys) * W + np.array(xs)
+
+
+# ----------------------------------------------------------------------------- pre-integration
+
+@pytest.mark.parametrize("dtype,dirs,order,shape,F", [
+    (np.uint8, DIRS4, 1, (37, 53), 0),
+    (np.uint8, DIRS4, 2, (29, 41), 0),
+    (np.float32, DIRS4, 2, (33, 47), 24),
+    (np.float32, DIRS4, 1, (70, 1100), 30),          # rows longer than one 1024-element chunk
+    (np.uint16, ((1, 0), (0, 1)), 3, (21, 19), 0),
+    (np.uint8, ((1, 1), (2, 1), (1, -2)), 1, (31, 26), 0),
+    (np.float32, ((0, 1), (1, 0), (1, 1), (1, -1)), 2, (150, 9), 20),   # tall: many line tiles
+])
+def test_preintegrate_bit_exact(dtype, dirs, order, shape, F):
+    note("preintegrate", dtype.__name__, dirs, order, shape)
+    rng = np.random.default_rng(hash((shape, order)) % 2 ** 32)
+    if dtype == np.float32:
+        img = rng.random(shape, dtype=np.float32)
+    else:
+        img = rng.integers(0, np.iinfo(dtype).max + 1, size=shape).astype(dtype)
+    cfg = bsf.Config(dirs=dirs, order=order, mode=bsf.STEPS_REAL, max_step=7.0)
+    G = bsf.preintegrate(cfg, torch.from_numpy(img).cuda(), F=F).cpu().numpy().view(np.uint64)
+    g = bsf.plan(cfg, *shape)
+    ref = O.preintegrate(img, dirs, order, F, (g.pad_top, g.pad_bottom, g.pad_left, g.pad_right))
+    np.testing.assert_array_equal(G, ref)
+
+
+# ----------------------------------------------------------------------------- integer steps
+
+@pytest.mark.parametrize("shape", [(150, 170), (1, 37), (37, 1), (2, 2)])
+def test_integer_steps_uint8_exact(shape):
+    note("int u8", shape)
+    d = WL.workload3(*shape)
+    cfg = cfg_of(d)
+    out, num, den, flags, F = run_forward(cfg, d["img"], d["steps"], want_num=True, want_den=True)
+    ref, rnum, rden = O.filter(d["img"], d["dirs"], 1, True, O.INT, d["steps"], want_int=True)
+    assert flags == 0
+    np.testing.assert_array_equal(num, rnum)
+    np.testing.assert_array_equal(den, rden)
+    assert_close(out, ref, 0, quantised=False, what="int u8")
+
+
+@pytest.mark.parametrize("shape", [(96, 112), (256, 256)])
+def test_integer_steps_float_image(shape):
+    note("int f32", shape)
+    d = WL.workload1(*shape)
+    cfg = cfg_of(d)
+    out, _, den, flags, F = run_forward(cfg, d["img"], d["steps"], want_den=True)
+    ref = O.filter(d["img"], d["dirs"], 1, True, O.INT, d["steps"])
+    assert flags == 0 and F >= 24      # samples are multiples of 2^-24: exact fixed point
+    assert_close(out, ref, F, quantised=False, what="int f32")
+
+
+def test_integer_steps_full_2048_uint8_sampled():
+    note("int u8 2048 full")
+    d = WL.workload3()
+    cfg = cfg_of(d)
+    out, num, den, flags, F = run_forward(cfg, d["img"], d["steps"], want_num=True, want_den=True)
+    pix = sample_pixels(2048, 2048, 1500, 7)
+    ref, rnum, rden = O.filter(d["img"], d["dirs"], 1, True, O.INT, d["steps"], pix=pix, want_int=True)
+    assert flags == 0
+    np.testing.assert_array_equal(num.reshape(-1)[pix], rnum)
+    np.testing.assert_array_equal(den.reshape(-1)[pix], rden)
+    # every pixel: den is the product of the steps, and num/den lies in [0, 255]
+    np.testing.assert_array_equal(den, np.prod(d["steps"].astype(np.int64), axis=0))
+    assert num.min() >= 0 and (num <= 255 * den).all()
+
+
+# ----------------------------------------------------------------------------- continuous steps
+
+def rand_steps(shape, planes, lo, hi, seed):
+    return np.random.default_rng(seed).uniform(lo, hi, size=(planes,) + shape).astype(np.float32)
+
+
+@pytest.mark.parametrize("shape,hi", [((70, 90), 9.0), ((17, 5), 4.0)])
+def test_continuous_order1(shape, hi):
+    note("real order1", shape)
+    img = np.random.default_rng(3).random(shape, dtype=np.float32)
+    steps = rand_steps(shape, 4, 1.0, hi, 4)
+    cfg = bsf.Config(order=1, max_step=hi)
+    out, _, _, flags, F = run_forward(cfg, img, steps)
+    ref = O.filter(img, DIRS4, 1, True, O.REAL, steps)
+    assert flags == 0
+    assert_close(out, ref, F, what="real order1")
+
+
+@pytest.mark.parametrize("shape,lo,hi,smooth", [
+    ((64, 72), 1.0, 12.0, False),     # independent steps per pixel: lanes disagree on R
+    ((50, 61), 1.0, 20.0, True),
+    ((3, 40), 1.0, 6.0, False),
+])
+def test_continuous_tied_order2(shape, lo, hi, smooth):
+    note("real tied order2", shape, smooth)
+    rng = np.random.default_rng(5)
+    img = rng.random(shape, dtype=np.float32)
+    if smooth:
+        steps = np.stack([WL.smooth(rng, *shape, lo, hi) for _ in range(4)]).astype(np.float32)
+    else:
+        steps = rand_steps(shape, 4, lo, hi, 6)
+    cfg = bsf.Config(order=2, max_step=hi)
+    out, _, _, flags, F = run_forward(cfg, img, steps)
+    ref = O.filter(img, DIRS4, 2, True, O.REAL, steps)
+    assert flags == 0
+    assert_close(out, ref, F, what="real tied order2")
+
+
+def test_continuous_untied_order2_generic():
+    note("real untied order2")
+    shape = (12, 14)
+    img = np.random.default_rng(8).random(shape, dtype=np.float32)
+    steps = rand_steps(shape, 8, 1.0, 3.5, 9)
+    cfg = bsf.Config(order=2, tied=False, max_step=3.5)
+    out, _, _, flags, F = run_forward(cfg, img, steps)
+    ref = O.filter(img, DIRS4, 2, False, O.REAL, steps)
+    assert_close(out, ref, F, what="real untied order2")
+
+
+def test_full_4096_order2_sampled():
+    note("real tied order2 4096 full")
+    d = WL.workload2()
+    cfg = cfg_of(d)
+    out, _, _, flags, F = run_forward(cfg, d["img"], d["steps"])
+    assert flags == 0
+    pix = sample_pixels(4096, 4096, 120, 11)
+    note("oracle on", len(pix), "pixels, F =", F)
+    ref = O.filter(d["img"], d["dirs"], 2, True, O.REAL, d["steps"], pix=pix)
+    rel = assert_close(out.reshape(-1)[pix], ref, F, what="4096 order2")
+    note("max rel err vs oracle", rel)
+    assert np.isfinite(out).all()
+
+
+# ----------------------------------------------------------------------------- status and edges
+
+def test_status_flags_for_bad_steps():
+    note("status flags")
+    shape = (20, 24)
+    img = np.random.default_rng(12).random(shape, dtype=np.float32)
+    steps = rand_steps(shape, 4, 1.0, 5.0, 13)
+    steps[0, 3, 4] = np.nan
+    steps[2, 10, 11] = 99.0          # above max_step
+    steps[1, 0, 0] = 0.25            # below 1
+    cfg = bsf.Config(order=2, max_step=5.0)
+    out, _, _, flags, F = run_forward(cfg, img, steps)
+    assert flags & bsf.FLAG_RANGE
+    assert np.isfinite(out).all()
+
+
+def test_explicit_frac_bits_overflow_flag():
+    note("overflow flag")
+    shape = (16, 16)
+    img = np.random.default_rng(14).random(shape, dtype=np.float32)
+    steps = rand_steps(shape, 4, 30.0, 31.0, 15)
+    cfg = bsf.Config(order=2, max_step=31.0, frac_bits=40)   # 40 + 1 + 8*5 bits > 62
+    _, _, _, flags, F = run_forward(cfg, img, steps)
+    assert F == 40 and flags & bsf.FLAG_OVERFLOW
+
+
+def test_empty_image_is_a_no_op():
+    note("empty")
+    cfg = bsf.Config(order=2, max_step=5.0)
+    img = torch.zeros((0, 7), device="cuda")
+    steps = torch.zeros((4, 0, 7), device="cuda")
+    out = bsf.filter_varying(cfg, img, steps)
+    assert out.shape == (0, 7)
+
+
+def test_deterministic_bits():
+    note("determinism")
+    shape = (40, 44)
+    img = np.random.default_rng(16).random(shape, dtype=np.float32)
+    steps = rand_steps(shape, 4, 1.0, 9.0, 17)
+    cfg = bsf.Config(order=2, max_step=9.0)
+    a = run_forward(cfg, img, steps)[0]
+    b = run_forward(cfg, img, steps)[0]
+    np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_plain_fp64_path_small_case_is_accurate():
+    """The plain FP64 path is exact enough on a tiny window at order 1 (its
+    cancellation error grows with the window and the order)."""
+    note("fp64 plain small")
+    shape = (20, 24)
+    img = np.random.default_rng(18).random(shape, dtype=np.float32)
+    steps = rand_steps(shape, 4, 1.0, 4.0, 19)
+    cfg = bsf.Config(order=1, max_step=4.0, arith=bsf.ARITH_FP64)
+    out, _, _, flags, F = run_forward(cfg, img, steps)
+    ref = O.filter(img, DIRS4, 1, True, O.REAL, steps)
+    assert np.abs(out - ref).max() < 1e-5
+
+
+def test_prepare_then_apply_with_other_steps():
+    """One pre-integration serves several step fields (the two banks of Alg. 2
+    share a running sum per bank): apply(steps2) on the window built with steps1
+    equals the one-call filter with steps2."""
+    note("prepare/apply")
+    shape = (45, 51)
+    rng = np.random.default_rng(20)
+    img = rng.random(shape, dtype=np.float32)
+    s1 = rand_steps(shape, 4, 1.0, 8.0, 21)
+    s2 = rand_steps(shape, 4, 1.0, 8.0, 22)
+    cfg = bsf.Config(order=2, max_step=8.0, frac_bits=24)
+    dev = torch.device("cuda:0")
+    ti, t1, t2 = (torch.from_numpy(a).to(dev) for a in (img, s1, s2))
+    ws = bsf.Workspace(bsf.plan(cfg, *shape).workspace_bytes, dev)
+    bsf.forward_prepare(cfg, ti, t1, ws)
+    out = torch.empty(shape, dtype=torch.float32, device=dev)
+    bsf.forward_apply(cfg, bsf.F32, t2, ws, out)
+    flags, F, _ = ws.status()
+    ref = bsf.filter_varying(cfg, ti, t2)
+    assert flags == 0 and F == 24
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), ref.cpu().numpy().view(np.uint32))
+    oref = O.filter(img, DIRS4, 2, True, O.REAL, s2)
+    assert_close(out.cpu().numpy(), oref, F, what="prepare/apply")

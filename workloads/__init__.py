@@ -63,36 +63,38 @@ def cov_field(theta, rho, sigma):
     return l1 * c * c + l2 * s * s, (l1 - l2) * s * c, l1 * s * s + l2 * c * c
 
 
-def steps_from_cov(C11, C12, C22, iters=60):
+def steps_from_cov(C11, C12, C22):
     """Grid steps (s1..s4) along (1,0), (0,1), (1,1), (1,-1) of the box spline
     whose covariance sum_k (s_k^2/12) u_k u_k^T equals C (eq. cov with the
     scale counted in lattice steps), choosing among the one-parameter family of
     solutions the one of least kurtosis: with A_k = s_k^2/12 and the free
     parameter t = A3 + A4, minimise the Frobenius norm of
     sum_k A_k^2 |u_k|^2 u_k u_k^T over t in [|C12|, min(C11, C22)].  That norm
-    is convex in t, so bisection on its derivative finds the minimiser.
-    Steps are floored at 1.  Vectorised over pixels."""
+    is convex in t.  Its derivative (over 4) is the cubic
+        h(t) = 8 t^3 - 6 S t^2 + 4 (C11^2 + C22^2 + 2 C12^2) t
+               - (C11^3 + C22^3 + C12^2 S),   S = C11 + C22,
+    strictly increasing on the whole line (its depressed form has
+    p = ((5 C11^2 - 6 C11 C22 + 5 C22^2)/16 + C12^2) > 0), so it has one real
+    root, found by Cardano's formula, polished by two Newton steps and clamped
+    to the feasible interval.  Steps are floored at 1.  Vectorised."""
     C11 = np.asarray(C11, dtype=np.float64)
     C12 = np.asarray(C12, dtype=np.float64)
     C22 = np.asarray(C22, dtype=np.float64)
     lo = np.abs(C12)
     hi = np.maximum(np.minimum(C11, C22), lo)
     c2 = C12 * C12
-
-    def dnorm2(t):
-        # Q11 = A1^2 + 2A3^2 + 2A4^2 = (C11 - t)^2 + t^2 + C12^2, likewise Q22,
-        # Q12 = 2A3^2 - 2A4^2 = 2 t C12; d/dt (Q11^2 + Q22^2 + 2 Q12^2) / 4:
-        q11 = (C11 - t) ** 2 + t * t + c2
-        q22 = (C22 - t) ** 2 + t * t + c2
-        return q11 * (2.0 * t - C11) + q22 * (2.0 * t - C22) + 4.0 * t * c2
-
-    a, b = lo.copy(), hi.copy()
-    for _ in range(iters):
-        m = 0.5 * (a + b)
-        pos = dnorm2(m) > 0.0
-        b = np.where(pos, m, b)
-        a = np.where(pos, a, m)
-    t = 0.5 * (a + b)
+    S = C11 + C22
+    a2, a1, a0 = -6.0 * S / 8.0, 4.0 * (C11 * C11 + C22 * C22 + 2.0 * c2) / 8.0, \
+        -(C11 ** 3 + C22 ** 3 + c2 * S) / 8.0
+    p = a1 - a2 * a2 / 3.0
+    q = 2.0 * a2 ** 3 / 27.0 - a2 * a1 / 3.0 + a0
+    disc = np.sqrt(np.maximum(q * q / 4.0 + p ** 3 / 27.0, 0.0))
+    t = np.cbrt(-q / 2.0 + disc) + np.cbrt(-q / 2.0 - disc) - a2 / 3.0
+    for _ in range(2):
+        h = 8.0 * t ** 3 - 6.0 * S * t * t + 8.0 * a1 * t + 8.0 * a0
+        dh = 24.0 * t * t - 12.0 * S * t + 8.0 * a1
+        t = t - h / dh
+    t = np.clip(t, lo, hi)
     A = [np.maximum(C11 - t, 0.0), np.maximum(C22 - t, 0.0),
          np.maximum((t + C12) / 2.0, 0.0), np.maximum((t - C12) / 2.0, 0.0)]
     return [np.maximum(np.sqrt(12.0 * Ak), 1.0) for Ak in A]
