@@ -158,17 +158,23 @@ bsf_status bsf_preintegrate(const bsf_config *cfg, bsf_dtype dtype, const void *
 /*
  * Forward filter (the whole hot path: fixed-point load, running sums, per-pixel
  * signed taps with the pixel's own steps, exact combination, normalisation).
- *   steps:   FP32 [planes][H][W].
- *   out:     FP32 [H][W] (nullable).
- *   out_num: int64 [H][W] numerators, integer images in integer mode only
- *            (nullable); out_den: int64 [H][W], prod_j s_j (nullable).
- *   G_save:  nullable; when given, the running sums are built there (layout of
- *            bsf_geometry) and left for bsf_filter_backward, and ws needs only
- *            workspace_bytes_g_external.
+ *   steps:       FP32 [planes][H][W].
+ *   out:         FP32 [H][W] (nullable).
+ *   out_num:     int64 [H][W] numerators, integer-step mode only (nullable):
+ *                the exact sample sum for integer images, the fixed-point sum
+ *                (value * 2^F) for float images.
+ *   out_den:     int64 [H][W], prod_j s_j, integer-step mode only (nullable).
+ *   dout_dsteps: FP32 [planes][H][W] (nullable, continuous steps): the
+ *                derivative of out(x) with respect to each of the pixel's own
+ *                step planes (right derivative where a step's phase is at a kink).
+ *                The filter is local in its steps, so this is all the backward
+ *                pass needs for the step gradient.
+ *   G_save:      nullable; when given, the running sums are built there (layout
+ *                of bsf_geometry) and ws needs only workspace_bytes_g_external.
  */
 bsf_status bsf_filter_varying(const bsf_config *cfg, bsf_dtype dtype, const void *img,
                               int64_t H, int64_t W, int64_t pitch, const float *steps,
-                              float *out, int64_t *out_num, int64_t *out_den,
+                              float *out, int64_t *out_num, int64_t *out_den, float *dout_dsteps,
                               void *G_save, void *ws, size_t ws_bytes, void *stream);
 
 /*
@@ -192,24 +198,27 @@ bsf_status bsf_forward_prepare(const bsf_config *cfg, bsf_dtype dtype, const voi
                                size_t ws_bytes, void *stream);
 bsf_status bsf_forward_apply(const bsf_config *cfg, bsf_dtype dtype, int64_t H, int64_t W,
                              const float *steps, const void *G, float *out, int64_t *out_num,
-                             int64_t *out_den, void *ws, size_t ws_bytes, void *stream);
+                             int64_t *out_den, float *dout_dsteps, void *ws, size_t ws_bytes,
+                             void *stream);
 
 /*
- * Adjoint of the forward filter for FP32 images with continuous steps
- * (spec differentiation): given the upstream gradient gout [H][W] of a
- * scalar loss L, writes
- *   grad_img   [H][W]          dL/df = K^T gout (nullable),
- *   grad_steps [planes][H][W]  dL/ds (nullable; right derivative where the
- *                              phase of a step is at a kink).
- * G_saved: the window left by bsf_filter_varying for the same img, steps and
- * configuration, or NULL to recompute it.  ws: at least
- * bsf_backward_workspace_bytes bytes.
+ * Adjoint of the forward filter with continuous steps (north-star
+ * differentiation).  Given the upstream gradient gout [H][W] of a scalar loss L:
+ *   grad_img   [H][W]          dL/df = K^T gout (nullable), computed as the scatter
+ *                              of the pixel's tap patterns weighted in fixed point
+ *                              by gout / prod s times the phase products, followed
+ *                              by the transposed running sums (exact int64; the
+ *                              rounding of those weights is the only error);
+ *   grad_steps [planes][H][W]  dL/ds = gout * dout_dsteps (nullable; needs the
+ *                              dout_dsteps saved by the forward call).
+ * The image itself is not needed: the filter is linear in it.  ws: at least
+ * bsf_backward_workspace_bytes bytes (status block, a window-sized int64
+ * accumulator and the scan carries).
  */
 size_t bsf_backward_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W);
-bsf_status bsf_filter_backward(const bsf_config *cfg, const float *img, int64_t H, int64_t W,
-                               int64_t pitch, const float *steps, const float *gout,
-                               float *grad_img, float *grad_steps, const void *G_saved,
-                               void *ws, size_t ws_bytes, void *stream);
+bsf_status bsf_filter_backward(const bsf_config *cfg, int64_t H, int64_t W, const float *steps,
+                               const float *gout, const float *dout_dsteps, float *grad_img,
+                               float *grad_steps, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Batched forward over B images of uneven sizes (FP32 images, one shared

@@ -70,12 +70,12 @@ def lib():
         L.bsf_workspace_init.argtypes = [P, sz, P]
         L.bsf_plan.argtypes = [cfgp, i64, i64, ctypes.POINTER(Geometry)]
         L.bsf_preintegrate.argtypes = [cfgp, i32, P, i64, i64, i64, i32, P, P, sz, P]
-        L.bsf_filter_varying.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, P, P, sz, P]
+        L.bsf_filter_varying.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, P, P, P, sz, P]
         L.bsf_forward_prepare.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, sz, P]
-        L.bsf_forward_apply.argtypes = [cfgp, i32, i64, i64, P, P, P, P, P, P, sz, P]
+        L.bsf_forward_apply.argtypes = [cfgp, i32, i64, i64, P, P, P, P, P, P, P, sz, P]
         L.bsf_backward_workspace_bytes.argtypes = [cfgp, i64, i64]
         L.bsf_backward_workspace_bytes.restype = sz
-        L.bsf_filter_backward.argtypes = [cfgp, P, i64, i64, i64, P, P, P, P, P, P, sz, P]
+        L.bsf_filter_backward.argtypes = [cfgp, i64, i64, P, P, P, P, P, P, sz, P]
         L.bsf_batched_workspace_bytes.argtypes = [cfgp, i32, ctypes.POINTER(_ImageDesc)]
         L.bsf_batched_workspace_bytes.restype = sz
         L.bsf_filter_batched.argtypes = [cfgp, i32, ctypes.POINTER(_ImageDesc), P, sz, P, i32]
@@ -230,9 +230,10 @@ def preintegrate(cfg: Config, img: torch.Tensor, F: int = 24, ws: Optional[Works
 
 def filter_varying(cfg: Config, img: torch.Tensor, steps: torch.Tensor, out: Optional[torch.Tensor] = None,
                    want_num: bool = False, want_den: bool = False, save_G: bool = False,
-                   ws: Optional[Workspace] = None):
+                   ws: Optional[Workspace] = None, dsteps: Optional[torch.Tensor] = None):
     """Forward space-variant filter.  Returns out (float32 [H][W]) and, on
-    request, num/den (int64, integer-step mode) and the saved window G."""
+    request, num/den (int64, integer-step mode) and the saved window G.  When
+    dsteps (float32 [planes][H][W]) is given it receives d out / d steps."""
     _check_image(img)
     H, W = img.shape
     _check_steps(cfg, steps, H, W)
@@ -249,9 +250,11 @@ def filter_varying(cfg: Config, img: torch.Tensor, steps: torch.Tensor, out: Opt
     need = g.workspace_bytes_g_external if save_G else g.workspace_bytes
     ws = ws or _workspace(dev, need)
     ws.ensure(need)
+    if dsteps is not None:
+        _check_steps(cfg, dsteps, H, W)
     _check(lib().bsf_filter_varying(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, img.stride(0),
-                                    _ptr(steps), _ptr(out), _ptr(num), _ptr(den), _ptr(G), ws.ptr(), ws.nbytes,
-                                    _stream(dev)),
+                                    _ptr(steps), _ptr(out), _ptr(num), _ptr(den), _ptr(dsteps), _ptr(G), ws.ptr(),
+                                    ws.nbytes, _stream(dev)),
            "bsf_filter_varying")
     res = [out]
     if want_num:
@@ -276,14 +279,65 @@ def forward_prepare(cfg: Config, img: torch.Tensor, steps: torch.Tensor, ws: Wor
 
 def forward_apply(cfg: Config, dtype_code: int, steps: torch.Tensor, ws: Workspace, out: torch.Tensor,
                   G: Optional[torch.Tensor] = None, num: Optional[torch.Tensor] = None,
-                  den: Optional[torch.Tensor] = None):
+                  den: Optional[torch.Tensor] = None, dsteps: Optional[torch.Tensor] = None):
     """Per-pixel taps of the running sums left by forward_prepare."""
     _, H, W = steps.shape
     _check_steps(cfg, steps, H, W)
     _check(lib().bsf_forward_apply(ctypes.byref(cfg.c()), int(dtype_code), H, W, _ptr(steps), _ptr(G), _ptr(out),
-                                   _ptr(num), _ptr(den), ws.ptr(), ws.nbytes, _stream(steps.device)),
+                                   _ptr(num), _ptr(den), _ptr(dsteps), ws.ptr(), ws.nbytes, _stream(steps.device)),
            "bsf_forward_apply")
     return out
+
+
+def filter_backward(cfg: Config, steps: torch.Tensor, gout: torch.Tensor, dsteps: Optional[torch.Tensor] = None,
+                    want_img: bool = True, want_steps: bool = True, ws: Optional[Workspace] = None):
+    """Adjoint: returns (grad_img or None, grad_steps or None).  grad_steps
+    needs dsteps (d out / d steps from the forward call)."""
+    _, H, W = steps.shape
+    _check_steps(cfg, steps, H, W)
+    if gout.dtype != torch.float32 or not gout.is_contiguous() or tuple(gout.shape) != (H, W):
+        raise ValueError("gout must be a contiguous float32 [H][W] device tensor")
+    dev = steps.device
+    gi = torch.empty((H, W), dtype=torch.float32, device=dev) if want_img else None
+    gs = torch.empty_like(steps) if want_steps else None
+    need = lib().bsf_backward_workspace_bytes(ctypes.byref(cfg.c()), H, W)
+    ws = ws or _workspace(dev, need)
+    ws.ensure(need)
+    _check(lib().bsf_filter_backward(ctypes.byref(cfg.c()), H, W, _ptr(steps), _ptr(gout), _ptr(dsteps), _ptr(gi),
+                                     _ptr(gs), ws.ptr(), ws.nbytes, _stream(dev)),
+           "bsf_filter_backward")
+    return gi, gs
+
+
+class _Filter(torch.autograd.Function):
+    """out = space-variant box-spline filter of img with per-pixel steps.  The
+    forward keeps d out / d steps (the filter is local in its steps); the
+    backward scatters the upstream gradient through the transposed taps and
+    running sums for the image."""
+
+    @staticmethod
+    def forward(ctx, img, steps, cfg):
+        need_s = ctx.needs_input_grad[1]
+        ds = torch.empty_like(steps) if need_s else None
+        out = filter_varying(cfg, img, steps, dsteps=ds)
+        ctx.cfg = cfg
+        ctx.save_for_backward(steps, ds if need_s else steps)
+        ctx.has_ds = need_s
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        steps, ds = ctx.saved_tensors
+        gi, gs = filter_backward(ctx.cfg, steps, gout.contiguous(), dsteps=ds if ctx.has_ds else None,
+                                 want_img=ctx.needs_input_grad[0], want_steps=ctx.has_ds)
+        return gi, gs, None
+
+
+def filter(img: torch.Tensor, steps: torch.Tensor, cfg: Config) -> torch.Tensor:
+    """Differentiable space-variant filter (continuous steps, float32 image)."""
+    if cfg.mode != STEPS_REAL or img.dtype != torch.float32:
+        raise ValueError("the differentiable filter takes a float32 image and continuous steps")
+    return _Filter.apply(img, steps, cfg)
 
 
 def version():

@@ -1,0 +1,265 @@
+// Adjoint of the space-variant filter with respect to the image.
+//
+// Forward, per pixel x:  out(x) = 2^-F / prod s(x) * sum_J c_J(x) J(x), where J
+// are the integer tap combinations of the running sums G = S f (one per choice
+// of operator per direction) and c_J the FP64 phase products.  Its transpose
+// sends the upstream gradient g back through the same taps and then through the
+// transposed running sums:
+//     grad_f = S^T  sum_x  sum_J  omega_J(x) B_J(. - x),
+// with B_J the integer tap pattern of J and omega_J(x) = g(x) c_J(x) / prod s(x).
+//
+// To keep the cancellation exact the weights are fixed point in the J basis,
+// omega_J = nearest(2^Fg g c_J / prod s), and everything after that is int64
+// modulo 2^64: the scatter of sum_J omega_J B_J into a window-sized array, and
+// the suffix sums S^T (the transposed, window-truncated running sums, last
+// direction first).  The result at every image pixel is bounded, so it comes
+// out exact; Fg is chosen from max |g| with 3 bits of headroom for the column
+// sums of the kernels.  The only error is the rounding of omega_J.
+#include "bsf_common.h"
+
+namespace bsf {
+namespace {
+
+constexpr int kTile = 16;
+constexpr int kColumnMarginBits = 3;
+
+__device__ __forceinline__ bool pixel_of_thread(int64_t H, int64_t W, int64_t &x, int64_t &y) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    x = (int64_t)blockIdx.x * kTile + (w & 1) * 8 + (lane & 7);
+    y = (int64_t)blockIdx.y * kTile + (w >> 1) * 8 + (lane >> 3);
+    return x < W && y < H;
+}
+
+__device__ __forceinline__ float clamp_step(float s, float max_step) { return fminf(fmaxf(s, 1.0f), max_step); }
+
+__device__ __forceinline__ int64_t fixed(double v) { return (int64_t)__builtin_rint(v); }
+
+__device__ __forceinline__ void atomic_add_i64(int64_t *p, int64_t v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+
+__global__ void k_adj_begin(int32_t *status) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) status[ST_G_ABSMAX_BITS] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_adj_gmax(const float *__restrict__ g, int64_t H, int64_t W,
+                                                  int32_t *status) {
+    __shared__ unsigned s_b[4];
+    unsigned b = 0;
+    for (int64_t y = blockIdx.x; y < H; y += gridDim.x)
+        for (int64_t x = threadIdx.x; x < W; x += blockDim.x) {
+            const float v = fabsf(g[y * W + x]);
+            if (v == v) b = max(b, __float_as_uint(v));
+        }
+    for (int d = 32; d >= 1; d >>= 1) b = max(b, (unsigned)__shfl_xor((int)b, d, 64));
+    if ((threadIdx.x & 63) == 0) s_b[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = max(b, s_b[k]);
+        atomicMax((unsigned *)&status[ST_G_ABSMAX_BITS], b);
+    }
+}
+
+__global__ void k_adj_choose_Fg(int32_t *status) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const float gmax = __uint_as_float((unsigned)status[ST_G_ABSMAX_BITS]);
+    int Fg = 0;
+    if (gmax > 0.0f) {
+        int e;
+        const double m = __builtin_frexp((double)gmax, &e);
+        const int eg = (m == 0.5) ? e - 1 : e;  // |g| <= 2^eg
+        Fg = 62 - eg - kColumnMarginBits;
+        if (Fg > 62) Fg = 62;
+        if (Fg < 0) Fg = 0;
+    }
+    status[ST_FG] = Fg;
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(int64_t *__restrict__ p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+// Tap patterns of the tied order-2 operators along one direction, tap index
+// p = 3 * cluster + sub (clusters T = 2R + sub, M = -2 + sub, B = -2R - 4 + sub):
+//   aa = T0 - 2 M1 + B2,  ab = T1 - M0 - M2 + B1,  bb = T2 - 2 M1 + B0.
+// expand3 gives the weight of tap p from the three operator weights.
+__device__ __forceinline__ int64_t expand3(int p, const int64_t v[3]) {
+    switch (p) {
+    case 0: return v[0];
+    case 1: return v[1];
+    case 2: return v[2];
+    case 3: return -v[1];
+    case 4: return -2 * (v[0] + v[2]);
+    case 5: return -v[1];
+    case 6: return v[2];
+    case 7: return v[1];
+    default: return v[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_adj_scatter_t2n4(AdjointArgs a) {
+    int64_t x, y;
+    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    const int64_t HW = a.H * a.W, idx = y * a.W + x;
+    const float g = a.gout[idx];
+    if (!(g != 0.0f)) return;  // zero (or NaN) upstream gradient scatters nothing
+    const int Fg = a.status[ST_FG];
+    int64_t o[4][9];
+    double w[4][3];
+    double den = 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float s = clamp_step(a.steps[a.plane[2 * k] * HW + idx], a.max_step);
+        const float t = (s - 1.0f) * 0.5f;
+        const float Rf = floorf(t);
+        const int64_t R = (int64_t)Rf, off = a.off[2 * k];
+        const double p = (double)(t - Rf), q = 1.0 - p;
+        w[k][0] = q * q;
+        w[k][1] = 2.0 * p * q;
+        w[k][2] = p * p;
+#pragma unroll
+        for (int sub = 0; sub < 3; ++sub) {
+            o[k][sub] = (2 * R + sub) * off;
+            o[k][3 + sub] = (-2 + sub) * off;
+            o[k][6 + sub] = (-2 * R - 4 + sub) * off;
+        }
+        den *= (double)s * (double)s;
+    }
+    const double fb = __builtin_ldexp((double)g / den, Fg);
+    int64_t *Gh = a.Ghat + (y + a.pad_top) * a.Wp + (x + a.pad_left);
+    for (int p0 = 0; p0 < 9; ++p0) {
+        // X1[a1][a2][a3] = sum_a0 C0(p0, a0) omega(a0, a1, a2, a3)
+        int64_t X1[27];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            const int a1 = q / 9, a2 = (q / 3) % 3, a3 = q % 3;
+            const double r = fb * w[1][a1] * w[2][a2] * w[3][a3];
+            int64_t v3[3];
+            v3[0] = fixed(r * w[0][0]);
+            v3[1] = fixed(r * w[0][1]);
+            v3[2] = fixed(r * w[0][2]);
+            X1[q] = expand3(p0, v3);
+        }
+        const int64_t b0 = o[0][p0];
+#pragma unroll
+        for (int p1 = 0; p1 < 9; ++p1) {
+            int64_t X2[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int64_t v3[3] = {X1[q], X1[9 + q], X1[18 + q]};
+                X2[q] = expand3(p1, v3);
+            }
+#pragma unroll
+            for (int p2 = 0; p2 < 9; ++p2) {
+                int64_t X3[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int64_t v3[3] = {X2[q], X2[3 + q], X2[6 + q]};
+                    X3[q] = expand3(p2, v3);
+                }
+                const int64_t b012 = b0 + o[1][p1] + o[2][p2];
+#pragma unroll
+                for (int p3 = 0; p3 < 9; ++p3) atomic_add_i64(Gh + b012 + o[3][p3], expand3(p3, X3));
+            }
+        }
+    }
+}
+
+// Any factor count: per factor the narrow and wide boxes, 2^M box choices e
+// with weights prod_j (e_j ? phi_j : 1 - phi_j), each spread over its 2^M taps.
+__global__ __launch_bounds__(256) void k_adj_scatter_generic(AdjointArgs a) {
+    int64_t x, y;
+    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    const int M = a.M;
+    const int64_t HW = a.H * a.W, idx = y * a.W + x;
+    const float g = a.gout[idx];
+    if (!(g != 0.0f)) return;
+    const int Fg = a.status[ST_FG];
+    int64_t pos[BSF_MAX_FACTORS][4];
+    double ph[BSF_MAX_FACTORS];
+    double den = 1.0;
+    for (int j = 0; j < M; ++j) {
+        const float s = clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
+        const float t = (s - 1.0f) * 0.5f;
+        const float R = floorf(t);
+        ph[j] = (double)(t - R);
+        const int64_t Ri = (int64_t)R;
+        pos[j][0] = Ri * a.off[j];
+        pos[j][1] = (-Ri - 1) * a.off[j];
+        pos[j][2] = (Ri + 1) * a.off[j];
+        pos[j][3] = (-Ri - 2) * a.off[j];
+        den *= (double)s;
+    }
+    const double fb = __builtin_ldexp((double)g / den, Fg);
+    int64_t *Gh = a.Ghat + (y + a.pad_top) * a.Wp + (x + a.pad_left);
+    const int n = 1 << M;
+    for (int e = 0; e < n; ++e) {
+        double w = fb;
+        for (int j = 0; j < M; ++j) w *= (e >> j & 1) ? ph[j] : 1.0 - ph[j];
+        const int64_t om = fixed(w);
+        if (om == 0) continue;
+        for (int t = 0; t < n; ++t) {
+            int64_t off = 0;
+            for (int j = 0; j < M; ++j) off += pos[j][2 * (e >> j & 1) + (t >> j & 1)];
+            atomic_add_i64(Gh + off, (__builtin_popcount(t) & 1) ? -om : om);
+        }
+    }
+}
+
+// grad_img = 2^-Fg * (S^T scattered)(x) on the image; grad_steps = g * dout/ds.
+__global__ __launch_bounds__(256) void k_adj_finish(const int64_t *__restrict__ Ghat, int64_t Wp, int64_t pad_top,
+                                                    int64_t pad_left, int64_t H, int64_t W,
+                                                    const int32_t *__restrict__ status, float *__restrict__ grad_img,
+                                                    const float *__restrict__ gout,
+                                                    const float *__restrict__ dsteps, float *__restrict__ grad_steps,
+                                                    int planes) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= W) return;
+    const int64_t HW = H * W;
+    const int Fg = status[ST_FG];
+    for (int64_t y = blockIdx.y; y < H; y += gridDim.y) {
+        const int64_t idx = y * W + x;
+        if (grad_img) grad_img[idx] = (float)__builtin_ldexp((double)Ghat[(y + pad_top) * Wp + (x + pad_left)], -Fg);
+        if (grad_steps) {
+            const float g = gout[idx];
+            for (int q = 0; q < planes; ++q) grad_steps[q * HW + idx] = g * dsteps[q * HW + idx];
+        }
+    }
+}
+
+}  // namespace
+
+bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *status, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_begin, dim3(1), dim3(64), 0, st, status);
+    BSF_HIP_CHECK(hipGetLastError());
+    int64_t blocks = p.H < 2048 ? p.H : 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_adj_gmax, dim3((unsigned)blocks), dim3(256), 0, st, a.gout, p.H, p.W, status);
+    BSF_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_adj_choose_Fg, dim3(1), dim3(64), 0, st, status);
+    BSF_HIP_CHECK(hipGetLastError());
+    const int64_t n = p.Hp * p.Wp;
+    int64_t fb = (n + 255) / 256;
+    if (fb > 65536) fb = 65536;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)fb), dim3(256), 0, st, a.Ghat, n);
+    BSF_HIP_CHECK(hipGetLastError());
+    dim3 grid((unsigned)((p.W + kTile - 1) / kTile), (unsigned)((p.H + kTile - 1) / kTile));
+    if (p.n_dirs == 4 && p.order == 2 && p.tied)
+        hipLaunchKernelGGL(k_adj_scatter_t2n4, grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_adj_scatter_generic, grid, dim3(256), 0, st, a);
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
+}
+
+bsf_status run_adjoint_finish(const Plan &p, const int64_t *Ghat, const int32_t *status, float *grad_img,
+                              const float *gout, const float *dsteps, float *grad_steps, hipStream_t st) {
+    dim3 grid((unsigned)((p.W + 255) / 256), (unsigned)(p.H < 4096 ? p.H : 4096));
+    hipLaunchKernelGGL(k_adj_finish, grid, dim3(256), 0, st, Ghat, p.Wp, p.pad_top, p.pad_left, p.H, p.W, status,
+                       grad_img, gout, dsteps, grad_steps, p.planes);
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
+}
+
+}  // namespace bsf

@@ -50,7 +50,7 @@ bsf_status make_plan(const bsf_config *cfg, int64_t H, int64_t W, Plan *p) {
     if (cfg->arith != BSF_ARITH_EXACT && cfg->arith != BSF_ARITH_FP64) return BSF_E_INVALID;
     if (!(cfg->max_step >= 1.0f) || !isfinite(cfg->max_step) || cfg->max_step > 1.0e6f) return BSF_E_INVALID;
     if (cfg->frac_bits < -1 || cfg->frac_bits > 62) return BSF_E_INVALID;
-    if (H < 0 || W < 0 || H > (int64_t(1) << 31) || W > (int64_t(1) << 31)) return BSF_E_INVALID;
+    if (H < 0 || W < 0 || H > (int64_t(1) << 18) || W > (int64_t(1) << 18)) return BSF_E_INVALID;
     int n_up = 0;
     for (int k = 0; k < cfg->n_dirs; ++k) {
         const int dx = cfg->dirs[2 * k], dy = cfg->dirs[2 * k + 1];
@@ -117,7 +117,7 @@ size_t ws_bytes_for(const Plan &p, bool g_internal) {
 }
 
 GatherArgs gather_args(const Plan &p, const void *G, const float *steps, float *out, int64_t *num, int64_t *den,
-                       const int32_t *status) {
+                       float *dsteps, const int32_t *status) {
     GatherArgs a;
     memset(&a, 0, sizeof(a));
     a.G = G;
@@ -130,6 +130,7 @@ GatherArgs gather_args(const Plan &p, const void *G, const float *steps, float *
     a.out = out;
     a.out_num = num;
     a.out_den = den;
+    a.dsteps = dsteps;
     a.status = status;
     a.max_step = p.max_step;
     a.M = p.M;
@@ -252,10 +253,11 @@ bsf_status prepare_impl(const bsf_config *cfg, bsf_dtype dtype, const void *img,
     return run_preintegrate(p, src, L.G, L.aux, L.status, st);
 }
 
-bsf_status apply_checks(const Plan &p, bsf_dtype dtype, int64_t *out_num, int64_t *out_den) {
+bsf_status apply_checks(const Plan &p, bsf_dtype dtype, int64_t *out_num, int64_t *out_den, float *dsteps) {
     if (src_kind_of(dtype) < 0) return BSF_E_INVALID;
     if (out_num && (p.mode != BSF_STEPS_INT || p.arith != BSF_ARITH_EXACT)) return BSF_E_INVALID;
     if (out_den && p.mode != BSF_STEPS_INT) return BSF_E_INVALID;
+    if (dsteps && p.mode != BSF_STEPS_REAL) return BSF_E_INVALID;
     return BSF_OK;
 }
 
@@ -272,12 +274,12 @@ bsf_status bsf_forward_prepare(const bsf_config *cfg, bsf_dtype dtype, const voi
 }
 
 bsf_status bsf_forward_apply(const bsf_config *cfg, bsf_dtype dtype, int64_t H, int64_t W, const float *steps,
-                             const void *G, float *out, int64_t *out_num, int64_t *out_den, void *ws,
-                             size_t ws_bytes, void *stream) {
+                             const void *G, float *out, int64_t *out_num, int64_t *out_den, float *dout_dsteps,
+                             void *ws, size_t ws_bytes, void *stream) {
     Plan p;
     bsf_status r = make_plan(cfg, H, W, &p);
     if (r != BSF_OK) return r;
-    r = apply_checks(p, dtype, out_num, out_den);
+    r = apply_checks(p, dtype, out_num, out_den, dout_dsteps);
     if (r != BSF_OK) return r;
     if (!ws || (H * W > 0 && !steps)) return BSF_E_INVALID;
     if (ws_bytes < ws_bytes_for(p, G == nullptr)) return BSF_E_WORKSPACE;
@@ -288,38 +290,72 @@ bsf_status bsf_forward_apply(const bsf_config *cfg, bsf_dtype dtype, int64_t H, 
     none.kind = src_kind_of(dtype);
     r = run_bound(p, none, steps, 0, L.status, st, true);
     if (r != BSF_OK) return r;
-    GatherArgs a = gather_args(p, L.G, steps, out, out_num, out_den, L.status);
+    GatherArgs a = gather_args(p, L.G, steps, out, out_num, out_den, dout_dsteps, L.status);
     return run_gather(p, a, st);
 }
 
 bsf_status bsf_filter_varying(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
                               int64_t pitch, const float *steps, float *out, int64_t *out_num, int64_t *out_den,
-                              void *G_save, void *ws, size_t ws_bytes, void *stream) {
+                              float *dout_dsteps, void *G_save, void *ws, size_t ws_bytes, void *stream) {
     Plan p;
     bsf_status r = make_plan(cfg, H, W, &p);
     if (r != BSF_OK) return r;
-    r = apply_checks(p, dtype, out_num, out_den);
+    r = apply_checks(p, dtype, out_num, out_den, dout_dsteps);
     if (r != BSF_OK) return r;
     WsLayout L;
     r = prepare_impl(cfg, dtype, img, H, W, pitch, steps, G_save, ws, ws_bytes, stream, p, L);
     if (r != BSF_OK || H * W == 0) return r;
-    GatherArgs a = gather_args(p, L.G, steps, out, out_num, out_den, L.status);
+    GatherArgs a = gather_args(p, L.G, steps, out, out_num, out_den, dout_dsteps, L.status);
     return run_gather(p, a, static_cast<hipStream_t>(stream));
 }
 
 size_t bsf_backward_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W) {
-    (void)cfg;
-    (void)H;
-    (void)W;
-    return 0;
+    Plan p;
+    if (make_plan(cfg, H, W, &p) != BSF_OK) return 0;
+    return ws_bytes_for(p, true);
 }
 
-bsf_status bsf_filter_backward(const bsf_config *cfg, const float *img, int64_t H, int64_t W, int64_t pitch,
-                               const float *steps, const float *gout, float *grad_img, float *grad_steps,
-                               const void *G_saved, void *ws, size_t ws_bytes, void *stream) {
-    (void)cfg; (void)img; (void)H; (void)W; (void)pitch; (void)steps; (void)gout; (void)grad_img;
-    (void)grad_steps; (void)G_saved; (void)ws; (void)ws_bytes; (void)stream;
-    return BSF_E_UNSUPPORTED;
+bsf_status bsf_filter_backward(const bsf_config *cfg, int64_t H, int64_t W, const float *steps, const float *gout,
+                               const float *dout_dsteps, float *grad_img, float *grad_steps, void *ws,
+                               size_t ws_bytes, void *stream) {
+    Plan p;
+    bsf_status r = make_plan(cfg, H, W, &p);
+    if (r != BSF_OK) return r;
+    if (p.mode != BSF_STEPS_REAL || p.arith != BSF_ARITH_EXACT) return BSF_E_UNSUPPORTED;
+    if (!ws) return BSF_E_INVALID;
+    if (H * W > 0 && (!steps || !gout)) return BSF_E_INVALID;
+    if (grad_steps && !dout_dsteps) return BSF_E_INVALID;
+    if (ws_bytes < ws_bytes_for(p, true)) return BSF_E_WORKSPACE;
+    if (H * W == 0 || (!grad_img && !grad_steps)) return BSF_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    WsLayout L = ws_layout(p, ws, nullptr);
+    if (grad_img) {
+        AdjointArgs a;
+        memset(&a, 0, sizeof(a));
+        const GatherArgs ga = gather_args(p, nullptr, steps, nullptr, nullptr, nullptr, nullptr, L.status);
+        a.Ghat = static_cast<int64_t *>(L.G);
+        a.Wp = p.Wp;
+        a.pad_top = p.pad_top;
+        a.pad_left = p.pad_left;
+        a.H = H;
+        a.W = W;
+        a.steps = steps;
+        a.gout = gout;
+        a.status = L.status;
+        a.max_step = p.max_step;
+        a.M = p.M;
+        a.order = p.order;
+        a.tied = p.tied;
+        a.n_dirs = p.n_dirs;
+        memcpy(a.off, ga.off, sizeof(a.off));
+        memcpy(a.plane, ga.plane, sizeof(a.plane));
+        r = run_adjoint_scatter(p, a, L.status, st);
+        if (r != BSF_OK) return r;
+        r = run_preintegrate_transpose(p, L.G, L.aux, st);
+        if (r != BSF_OK) return r;
+    }
+    return run_adjoint_finish(p, static_cast<const int64_t *>(L.G), L.status, grad_img, gout, dout_dsteps,
+                              grad_steps, st);
 }
 
 size_t bsf_batched_workspace_bytes(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs) {

@@ -64,6 +64,7 @@ struct GatherArgs {
     int64_t H, W;
     const float *steps;     // [planes][H][W]
     float *out;             // nullable
+    float *dsteps;          // nullable: d out / d step, [planes][H][W] (continuous steps)
     int64_t *out_num;       // nullable
     int64_t *out_den;       // nullable
     const int32_t *status;  // F at status[ST_F_USED]
@@ -80,22 +81,28 @@ bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st);
 bsf_status run_bound(const Plan &p, const Src &src, const float *steps, int32_t F_request, int32_t *status,
                      hipStream_t st, bool recheck);
 
-// Adjoint (adjoint.hip).
+// Adjoint (adjoint.hip).  Status words of the backward pass live in the
+// workspace's status block after the forward ones.
+enum AdjStatusWord : int {
+    ST_G_ABSMAX_BITS = 16,  // scratch: float bits of max |gout|
+    ST_FG = 17,             // fixed-point bits of the scattered adjoint weights
+};
+
 struct AdjointArgs {
-    const void *G;          // forward running sums (int64) for the step gradient
-    void *Ghat;             // int64 window accumulating the scattered stencils
+    int64_t *Ghat;           // int64 window accumulating the scattered stencils
     int64_t Wp, pad_top, pad_left;
     int64_t H, W;
     const float *steps;
     const float *gout;
-    float *grad_steps;      // nullable
-    const int32_t *status;  // F at status[ST_F_USED]
-    int32_t *gstatus;       // fixed-point bits of the adjoint scatter at [0]
+    const int32_t *status;   // Fg at status[ST_FG]
     float max_step;
     int M, order, tied, n_dirs;
     int32_t off[BSF_MAX_FACTORS];
     int32_t plane[BSF_MAX_FACTORS];
 };
+bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *status, hipStream_t st);
+bsf_status run_adjoint_finish(const Plan &p, const int64_t *Ghat, const int32_t *status, float *grad_img,
+                              const float *gout, const float *dsteps, float *grad_steps, hipStream_t st);
 
 }  // namespace bsf
 

@@ -33,6 +33,18 @@ __device__ __forceinline__ bool pixel_of_thread(int64_t H, int64_t W, int64_t &x
     return x < W && y < H;
 }
 
+// Wavefront of WX x (64/WX) pixels; the four wavefronts of a workgroup stack
+// vertically, so the workgroup covers WX x (256/WX).  Wider wavefronts touch
+// fewer rows (cache lines) per tap load.
+template <int WX>
+__device__ __forceinline__ bool pixel_of_thread_wx(int64_t H, int64_t W, int64_t &x, int64_t &y) {
+    constexpr int WY = 64 / WX;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    x = (int64_t)blockIdx.x * WX + (lane % WX);
+    y = (int64_t)blockIdx.y * (4 * WY) + w * WY + (lane / WX);
+    return x < W && y < H;
+}
+
 __device__ __forceinline__ float clamp_step(float s, float max_step) {
     // NaN -> 1 (fmaxf returns the non-NaN operand); keeps every tap in the window
     return fminf(fmaxf(s, 1.0f), max_step);
@@ -250,11 +262,14 @@ __global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs a) {
         den *= (double)s;
     }
     double tot = 0.0;
+    double dtot[BSF_MAX_FACTORS];
+    for (int j = 0; j < M; ++j) dtot[j] = 0.0;
+    const bool want_d = a.dsteps != nullptr;
     const int n = 1 << M;
     for (int e = 0; e < n; ++e) {
         double w = 1.0;
         for (int j = 0; j < M; ++j) w *= (e >> j & 1) ? ph[j] : 1.0 - ph[j];
-        if (w == 0.0) continue;
+        if (w == 0.0 && !want_d) continue;
         V J = V(0);
         for (int t = 0; t < n; ++t) {
             int64_t o = 0;
@@ -263,12 +278,32 @@ __global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs a) {
             else J += G[o];
         }
         tot += w * (double)J;
+        if (want_d) {
+            // d w / d phi_j: the product over the other factors, signed by the box choice
+            for (int j = 0; j < M; ++j) {
+                double dw = (e >> j & 1) ? 1.0 : -1.0;
+                for (int l = 0; l < M; ++l)
+                    if (l != j) dw *= (e >> l & 1) ? ph[l] : 1.0 - ph[l];
+                dtot[j] += dw * (double)J;
+            }
+        }
     }
-    if constexpr (std::is_integral_v<V>) {
-        const int F = a.status[ST_F_USED];
-        if (a.out) a.out[idx] = (float)(ldexp_neg(tot, F) / den);
-    } else {
-        if (a.out) a.out[idx] = (float)(tot / den);
+    int F = 0;
+    if constexpr (std::is_integral_v<V>) F = a.status[ST_F_USED];
+    const double outv = ldexp_neg(tot, F) / den;
+    if (a.out) a.out[idx] = (float)outv;
+    if (want_d) {
+        // plane q collects its factors: d out / d s_j = (1/2) dJ-term / den - out / s_j
+        const int planes = a.tied ? a.n_dirs : M;
+        for (int q = 0; q < planes; ++q) {
+            double d = 0.0;
+            for (int j = 0; j < M; ++j) {
+                if (a.plane[j] != q) continue;
+                const double s = (double)clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
+                d += 0.5 * ldexp_neg(dtot[j], F) / den - outv / s;
+            }
+            a.dsteps[q * HW + idx] = (float)d;
+        }
     }
 }
 
@@ -299,56 +334,85 @@ __device__ __forceinline__ void offsets9(int32_t R, int32_t off, int32_t o[9]) {
     o[6] = b; o[7] = b + off; o[8] = b + 2 * off;
 }
 
-// acc[a1][a2][a3] += sum_{p1,p2,p3} C1 C2 C3 G[b + o1[p1] + o2[p2] + o3[p3]]
-// (directions 1..3 of the contraction; direction 3 innermost).
-// Offsets are 32-bit element indices into the window (the launcher checks the
-// window has fewer than 2^31 elements), so every load is base + 32-bit offset.
-__device__ __forceinline__ void contract3(const int64_t *__restrict__ G, int32_t b, const int32_t o1[9],
-                                          const int32_t o2[9], const int32_t o3[9], int64_t acc[27]) {
+// One 8-byte running-sum value.  Offsets are 32-bit byte offsets from the
+// window base (the launcher checks the window is below 4 GiB); forming the
+// address as base pointer + offset lets constant deltas become load
+// immediates, so a cluster of three consecutive taps costs one address add.
+__device__ __forceinline__ int64_t ldG(const char *__restrict__ p) {
+    return *reinterpret_cast<const int64_t *>(p);
+}
+
+// acc[a1][a2][a3] += sum over the 9 x 9 x 9 taps (p1, p2, p3) of directions
+// 1..3 of C1 C2 C3 G[b + o1(p1) + o2(p2) + o3(p3)], direction 3 innermost.
+// Tap index p = 3 * cluster + sub, clusters T (2R + sub), M (-2 + sub),
+// B (-2R - 4 + sub); per direction the operators are
+//   aa = T0 + B2 - 2 M1,  ab = T1 + B1 - M0 - M2,  bb = T2 + B0 - 2 M1.
+// The two inner levels keep positive and negative parts apart so that every
+// fold is an add; the sign of the direction-1 tap is applied once per p1.
+template <bool CONTIG>
+__device__ __forceinline__ void contract3(const char *__restrict__ Gb, uint32_t b, const int32_t cT[4],
+                                          const int32_t cB[4], const int32_t st[4], int64_t acc[27]) {
+    const int32_t st3 = CONTIG ? 8 : st[3];
 #pragma unroll
     for (int p1 = 0; p1 < 9; ++p1) {
+        const int c1 = p1 / 3, s1 = p1 % 3;
+        const uint32_t b1 = b + (uint32_t)((c1 == 0 ? cT[1] : c1 == 1 ? -2 * st[1] : cB[1]) + s1 * st[1]);
         int64_t ipos[9], ineg[9];  // [a2][a3]
 #pragma unroll
-        for (int i = 0; i < 9; ++i) { ipos[i] = 0; ineg[i] = 0; }
+        for (int q = 0; q < 9; ++q) { ipos[q] = 0; ineg[q] = 0; }
 #pragma unroll
         for (int p2 = 0; p2 < 9; ++p2) {
-            const int32_t bb = b + o1[p1] + o2[p2];
-            int64_t v[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) v[i] = G[(uint32_t)(bb + o3[i])];
-            const int64_t m2 = v[4] * 2;
-            int64_t s[3];
-            s[0] = v[0] + v[8] - m2;          // aa
-            s[1] = v[1] + v[7] - v[3] - v[5]; // ab
-            s[2] = v[2] + v[6] - m2;          // bb
-            // fold direction 2 (tap p2) into [a2][a3]
-            if (p2 == 0 || p2 == 8) { for (int i = 0; i < 3; ++i) ipos[0 * 3 + i] += s[i]; }
-            if (p2 == 1 || p2 == 7) { for (int i = 0; i < 3; ++i) ipos[1 * 3 + i] += s[i]; }
-            if (p2 == 2 || p2 == 6) { for (int i = 0; i < 3; ++i) ipos[2 * 3 + i] += s[i]; }
-            if (p2 == 3 || p2 == 5) { for (int i = 0; i < 3; ++i) ineg[1 * 3 + i] += s[i]; }
-            if (p2 == 4) {
-                for (int i = 0; i < 3; ++i) {
-                    ineg[0 * 3 + i] += 2 * s[i];
-                    ineg[2 * 3 + i] += 2 * s[i];
-                }
+            const int c2 = p2 / 3, s2 = p2 % 3;
+            const uint32_t b2 = b1 + (uint32_t)((c2 == 0 ? cT[2] : c2 == 1 ? -2 * st[2] : cB[2]) + s2 * st[2]);
+            const char *pT = Gb + (uint32_t)(b2 + (uint32_t)cT[3]);
+            const char *pM = Gb + b2;
+            const char *pB = Gb + (uint32_t)(b2 + (uint32_t)cB[3]);
+            const int64_t T0 = ldG(pT), T1 = ldG(pT + st3), T2 = ldG(pT + 2 * st3);
+            const int64_t M0 = ldG(pM - 2 * st3), M1 = ldG(pM - st3), M2 = ldG(pM);
+            const int64_t B0 = ldG(pB), B1 = ldG(pB + st3), B2 = ldG(pB + 2 * st3);
+            const int64_t P0 = T0 + B2, P1 = T1 + B1, P2 = T2 + B0, N1 = M0 + M2;
+            if (c2 != 1) {  // T or B tap: +1 on operator a2
+                const int a2 = (c2 == 0) ? s2 : 2 - s2;
+                ipos[a2 * 3 + 0] += P0; ipos[a2 * 3 + 1] += P1; ipos[a2 * 3 + 2] += P2;
+                ineg[a2 * 3 + 0] += 2 * M1; ineg[a2 * 3 + 1] += N1; ineg[a2 * 3 + 2] += 2 * M1;
+            } else if (s2 != 1) {  // M0, M2: -1 on ab
+                ipos[3] += 2 * M1; ipos[4] += N1; ipos[5] += 2 * M1;
+                ineg[3] += P0; ineg[4] += P1; ineg[5] += P2;
+            } else {  // M1: -2 on aa and bb
+                ipos[0] += 4 * M1; ipos[1] += 2 * N1; ipos[2] += 4 * M1;
+                ineg[0] += 2 * P0; ineg[1] += 2 * P1; ineg[2] += 2 * P2;
+                ipos[6] += 4 * M1; ipos[7] += 2 * N1; ipos[8] += 4 * M1;
+                ineg[6] += 2 * P0; ineg[7] += 2 * P1; ineg[8] += 2 * P2;
             }
         }
-        // fold direction 1 (tap p1) into acc[a1][a2][a3]
-        const bool neg = (p1 >= 3 && p1 <= 5);
-        int64_t in[9];
+        if (c1 != 1) {
+            const int a1 = (c1 == 0) ? s1 : 2 - s1;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) in[i] = neg ? ineg[i] - ipos[i] : ipos[i] - ineg[i];
-        if (p1 == 0 || p1 == 8) { for (int i = 0; i < 9; ++i) acc[0 * 9 + i] += in[i]; }
-        if (p1 == 1 || p1 == 7) { for (int i = 0; i < 9; ++i) acc[1 * 9 + i] += in[i]; }
-        if (p1 == 2 || p1 == 6) { for (int i = 0; i < 9; ++i) acc[2 * 9 + i] += in[i]; }
-        if (p1 == 3 || p1 == 5) { for (int i = 0; i < 9; ++i) acc[1 * 9 + i] += in[i]; }
-        if (p1 == 4) {
-            for (int i = 0; i < 9; ++i) {
-                acc[0 * 9 + i] += 2 * in[i];
-                acc[2 * 9 + i] += 2 * in[i];
+            for (int q = 0; q < 9; ++q) acc[a1 * 9 + q] += ipos[q] - ineg[q];
+        } else if (s1 != 1) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) acc[9 + q] += ineg[q] - ipos[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int64_t d = ineg[q] - ipos[q];
+                acc[q] += 2 * d;
+                acc[18 + q] += 2 * d;
             }
         }
     }
+}
+
+// Phase weights of one tied order-2 direction, (1-phi)^2, 2 phi (1-phi), phi^2
+// for the operators aa, ab, bb, and their derivatives with respect to phi.
+__device__ __forceinline__ void phase_weights(float phf, double w[3], double dw[3]) {
+    const double p = (double)phf, q = 1.0 - p;
+    w[0] = q * q;
+    w[1] = 2.0 * p * q;
+    w[2] = p * p;
+    dw[0] = -2.0 * q;
+    dw[1] = 2.0 - 4.0 * p;
+    dw[2] = 2.0 * p;
 }
 
 __device__ __forceinline__ double contract_fp(const int64_t acc[27], const double w1[3], const double w2[3],
@@ -369,45 +433,51 @@ __device__ __forceinline__ double contract_fp(const int64_t acc[27], const doubl
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_gather_t2n4(GatherArgs a) {
+// Direction 0 is outermost: its taps are visited in an order that finishes
+// one operator at a time, so only the 27 values J[a0][.][.][.] of the current
+// operator a0 are live:
+//   aa: -2 M1, + T0, + B2;   bb: -2 M1, + T2, + B0;   ab: -(M0 + M2), + T1, + B1
+// (M1 is visited twice, 10 steps in all).  WAVES bounds the registers so that
+// that many wavefronts fit on a SIMD.
+template <bool CONTIG, int WAVES, int WX>
+__global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs a) {
     int64_t x, y;
-    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    if (!pixel_of_thread_wx<WX>(a.H, a.W, x, y)) return;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
-    const int64_t *G = static_cast<const int64_t *>(a.G);
-    const int32_t base = (int32_t)((y + a.pad_top) * a.Wp + (x + a.pad_left));
-    // contraction direction k uses config factor 2k (tied: both copies share the plane)
-    int32_t o[4][9];
-    double w[4][3];
+    const char *Gb = static_cast<const char *>(a.G);
+    const uint32_t base = (uint32_t)(((y + a.pad_top) * a.Wp + (x + a.pad_left)) * 8);
+    // contraction direction k is config factor 2k (tied: both copies share a plane)
+    int32_t cT[4], cB[4], st[4];
+    float ph[4], sk[4];
     double den = 1.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const float s = clamp_step(a.steps[a.plane[2 * k] * HW + idx], a.max_step);
         const float t = (s - 1.0f) * 0.5f;
         const float Rf = floorf(t);
-        const double ph = (double)(t - Rf);
-        offsets9((int32_t)Rf, a.off[2 * k], o[k]);
-        w[k][0] = (1.0 - ph) * (1.0 - ph);
-        w[k][1] = 2.0 * ph * (1.0 - ph);
-        w[k][2] = ph * ph;
+        const int32_t R = (int32_t)Rf;
+        st[k] = a.off[2 * k] * 8;
+        ph[k] = t - Rf;
+        sk[k] = s;
+        cT[k] = 2 * R * st[k];
+        cB[k] = (-2 * R - 4) * st[k];
         den *= (double)s * (double)s;
     }
-    // direction 0 outermost: visit (tap, action) so one operator finishes at a time
-    //   aa: -2 M1, + T0, + B2;   bb: -2 M1, + T2, + B0;   ab: -(M0 + M2), + T1, + B1
+    double dtot[4] = {0.0, 0.0, 0.0, 0.0};
     constexpr int kSeq[10] = {4, 0, 8, 4, 2, 6, 3, 5, 1, 7};
     double tot = 0.0;
     int64_t acc[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) acc[i] = 0;
+    for (int q = 0; q < 27; ++q) acc[q] = 0;
     for (int i = 0; i < 10; ++i) {
         const int p0 = kSeq[i];
         if (i == 0 || i == 3 || i == 6) {
 #pragma unroll
             for (int q = 0; q < 27; ++q) acc[q] = 0;
         }
-        int32_t ob = o[0][0];
-#pragma unroll
-        for (int q = 1; q < 9; ++q) ob = (p0 == q) ? o[0][q] : ob;
-        contract3(G, base + ob, o[1], o[2], o[3], acc);
+        const int c0 = p0 / 3, s0 = p0 % 3;
+        const int32_t o0 = (c0 == 0 ? cT[0] : c0 == 1 ? -2 * st[0] : cB[0]) + s0 * st[0];
+        contract3<CONTIG>(Gb, base + (uint32_t)o0, cT, cB, st, acc);
         if (i == 0 || i == 3) {
 #pragma unroll
             for (int q = 0; q < 27; ++q) acc[q] = -2 * acc[q];
@@ -416,135 +486,30 @@ __global__ __launch_bounds__(256) void k_gather_t2n4(GatherArgs a) {
 #pragma unroll
             for (int q = 0; q < 27; ++q) acc[q] = -acc[q];
         }
-        if (i == 2) tot += w[0][0] * contract_fp(acc, w[1], w[2], w[3]);
-        if (i == 5) tot += w[0][2] * contract_fp(acc, w[1], w[2], w[3]);
-        if (i == 9) tot += w[0][1] * contract_fp(acc, w[1], w[2], w[3]);
-    }
-    const int F = a.status[ST_F_USED];
-    if (a.out) a.out[idx] = (float)(ldexp_neg(tot, F) / den);
-}
-
-// Same contraction, organised to keep few values live: the two outer
-// directions are walked operator pair by operator pair (a0, a1), so only the 9
-// values J[a0][a1][.][.] accumulate; every outer tap pair (t0, t1) forms the
-// 81-tap inner block.  Offsets are 32-bit byte offsets from the window base
-// (window < 4 GiB), the inner block keeps positive and negative parts apart
-// so it only adds, and the sign and power of two of the outer coefficients are
-// applied once per block.  10 x 10 outer tap pairs: 8100 loads per pixel.
-struct Tap {
-    int8_t cluster, sub, coef;  // cluster 0 = T, 1 = M, 2 = B
-};
-__constant__ Tap kOpTaps[3][4] = {
-    {{0, 0, 1}, {1, 1, -2}, {2, 2, 1}, {0, 0, 0}},    // aa
-    {{0, 1, 1}, {1, 0, -1}, {1, 2, -1}, {2, 1, 1}},   // ab
-    {{0, 2, 1}, {1, 1, -2}, {2, 0, 1}, {0, 0, 0}},    // bb
-};
-__constant__ int kOpN[3] = {3, 4, 3};
-
-__device__ __forceinline__ int64_t ld64(const char *__restrict__ Gb, uint32_t byte_off) {
-    return *reinterpret_cast<const int64_t *>(Gb + byte_off);
-}
-
-__global__ __launch_bounds__(256) void k_gather_t2n4_pairs(GatherArgs a) {
-    int64_t x, y;
-    if (!pixel_of_thread(a.H, a.W, x, y)) return;
-    const int64_t HW = a.H * a.W, idx = y * a.W + x;
-    const char *Gb = static_cast<const char *>(a.G);
-    const uint32_t base = (uint32_t)(((y + a.pad_top) * a.Wp + (x + a.pad_left)) * 8);
-    int32_t cT[4], cB[4], cM[4], st[4];
-    float ph[4];
-    double den = 1.0;
+        if (i == 2 || i == 5 || i == 9) {
+            double w[4][3], dw[4][3];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float s = clamp_step(a.steps[a.plane[2 * k] * HW + idx], a.max_step);
-        const float t = (s - 1.0f) * 0.5f;
-        const float Rf = floorf(t);
-        const int32_t R = (int32_t)Rf, off8 = a.off[2 * k] * 8;
-        ph[k] = t - Rf;
-        st[k] = off8;
-        cT[k] = 2 * R * off8;
-        cM[k] = -2 * off8;
-        cB[k] = (-2 * R - 4) * off8;
-        den *= (double)s * (double)s;
-    }
-    double tot = 0.0;
-    for (int a0 = 0; a0 < 3; ++a0) {
-        for (int a1 = 0; a1 < 3; ++a1) {
-            int64_t acc[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) acc[i] = 0;
-            for (int i0 = 0; i0 < kOpN[a0]; ++i0) {
-                const Tap t0 = kOpTaps[a0][i0];
-                const int32_t o0 = (t0.cluster == 0 ? cT[0] : t0.cluster == 1 ? cM[0] : cB[0]) + t0.sub * st[0];
-                for (int i1 = 0; i1 < kOpN[a1]; ++i1) {
-                    const Tap t1 = kOpTaps[a1][i1];
-                    const int32_t o1 =
-                        (t1.cluster == 0 ? cT[1] : t1.cluster == 1 ? cM[1] : cB[1]) + t1.sub * st[1];
-                    const uint32_t b = base + (uint32_t)(o0 + o1);
-                    int64_t ipos[9], ineg[9];
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) { ipos[i] = 0; ineg[i] = 0; }
-#pragma unroll
-                    for (int p2 = 0; p2 < 9; ++p2) {
-                        const int c2 = p2 / 3, s2 = p2 % 3;
-                        const uint32_t b2 =
-                            b + (uint32_t)((c2 == 0 ? cT[2] : c2 == 1 ? cM[2] : cB[2]) + s2 * st[2]);
-                        const uint32_t bT = b2 + (uint32_t)cT[3], bM = b2 + (uint32_t)cM[3],
-                                       bB = b2 + (uint32_t)cB[3];
-                        const int64_t T0 = ld64(Gb, bT), T1 = ld64(Gb, bT + st[3]), T2 = ld64(Gb, bT + 2 * st[3]);
-                        const int64_t M0 = ld64(Gb, bM), M1 = ld64(Gb, bM + st[3]), M2 = ld64(Gb, bM + 2 * st[3]);
-                        const int64_t B0 = ld64(Gb, bB), B1 = ld64(Gb, bB + st[3]), B2 = ld64(Gb, bB + 2 * st[3]);
-                        // aa = T0 + B2 - 2 M1, ab = T1 + B1 - (M0 + M2), bb = T2 + B0 - 2 M1
-                        const int64_t P[3] = {T0 + B2, T1 + B1, T2 + B0};
-                        const int64_t m1x2 = M1 * 2;
-                        const int64_t N[3] = {m1x2, M0 + M2, m1x2};
-                        // direction-2 tap p2 = (c2, s2): T/B taps are +1, M taps -1 or -2
-                        if (c2 != 1) {
-                            const int a2 = (c2 == 0) ? s2 : 2 - s2;
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) { ipos[a2 * 3 + i] += P[i]; ineg[a2 * 3 + i] += N[i]; }
-                        } else if (s2 != 1) {
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) { ipos[3 + i] += N[i]; ineg[3 + i] += P[i]; }
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) {
-                                ipos[0 + i] += 2 * N[i]; ineg[0 + i] += 2 * P[i];
-                                ipos[6 + i] += 2 * N[i]; ineg[6 + i] += 2 * P[i];
-                            }
-                        }
-                    }
-                    const int c = t0.coef * t1.coef;   // +-1, +-2 or 4
-                    const int sh = (c == 1 || c == -1) ? 0 : (c == 4 ? 2 : 1);
-                    if (c > 0) {
-#pragma unroll
-                        for (int i = 0; i < 9; ++i) acc[i] += (ipos[i] - ineg[i]) << sh;
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < 9; ++i) acc[i] += (ineg[i] - ipos[i]) << sh;
-                    }
-                }
+            for (int k = 0; k < 4; ++k) phase_weights(ph[k], w[k], dw[k]);
+            const int a0 = (i == 2) ? 0 : (i == 5) ? 2 : 1;
+            const double r = contract_fp(acc, w[1], w[2], w[3]);
+            tot += w[0][a0] * r;
+            if (a.dsteps) {
+                dtot[0] += dw[0][a0] * r;
+                dtot[1] += w[0][a0] * contract_fp(acc, dw[1], w[2], w[3]);
+                dtot[2] += w[0][a0] * contract_fp(acc, w[1], dw[2], w[3]);
+                dtot[3] += w[0][a0] * contract_fp(acc, w[1], w[2], dw[3]);
             }
-            // J[a0][a1][a2][a3] complete: apply the FP64 phase weights
-            const double q2 = 1.0 - ph[2], p2w = ph[2], q3 = 1.0 - ph[3], p3w = ph[3];
-            const double w2[3] = {q2 * q2, 2.0 * p2w * q2, p2w * p2w};
-            const double w3[3] = {q3 * q3, 2.0 * p3w * q3, p3w * p3w};
-            double r = 0.0;
-#pragma unroll
-            for (int a2 = 0; a2 < 3; ++a2) {
-                double r2 = 0.0;
-#pragma unroll
-                for (int a3 = 0; a3 < 3; ++a3) r2 += w3[a3] * (double)acc[a2 * 3 + a3];
-                r += w2[a2] * r2;
-            }
-            const double p0w = ph[0], q0 = 1.0 - p0w, p1w = ph[1], q1 = 1.0 - p1w;
-            const double w0 = a0 == 0 ? q0 * q0 : a0 == 1 ? 2.0 * p0w * q0 : p0w * p0w;
-            const double w1 = a1 == 0 ? q1 * q1 : a1 == 1 ? 2.0 * p1w * q1 : p1w * p1w;
-            tot += w0 * w1 * r;
         }
     }
     const int F = a.status[ST_F_USED];
-    if (a.out) a.out[idx] = (float)(ldexp_neg(tot, F) / den);
+    const double outv = ldexp_neg(tot, F) / den;
+    if (a.out) a.out[idx] = (float)outv;
+    if (a.dsteps) {
+        // d phi / d s = 1/2, and the step of direction k enters prod s twice
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            a.dsteps[a.plane[2 * k] * HW + idx] = (float)(0.5 * ldexp_neg(dtot[k], F) / den - 2.0 * outv / sk[k]);
+    }
 }
 
 // Plain FP64 counterpart: FP64 running sums and FP64 tap weights
@@ -634,10 +599,18 @@ bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st) {
             if (fp64) hipLaunchKernelGGL((k_gather_int<double, 0>), grid, block, 0, st, a);
             else hipLaunchKernelGGL((k_gather_int<int64_t, 0>), grid, block, 0, st, a);
         }
-    } else if (p.n_dirs == 4 && p.order == 2 && p.tied && p.Hp * p.Wp < (int64_t(1) << 31)) {
+    } else if (p.n_dirs == 4 && p.order == 2 && p.tied && p.Hp * p.Wp * 8 < (int64_t(1) << 32)) {
+        const int v = t2n4_variant();
+        const bool contig = a.off[6] == 1;
+        // wavefront width in pixels (the tuner's choice)
+        const int wx = v == 1 ? 8 : v == 3 ? 32 : v == 4 ? 64 : 16;
+        dim3 g2((unsigned)((p.W + wx - 1) / wx), (unsigned)((p.H + 256 / wx - 1) / (256 / wx)));
         if (fp64) hipLaunchKernelGGL(k_gather_t2n4_fp64, grid, block, 0, st, a);
-        else if (t2n4_variant() == 1) hipLaunchKernelGGL(k_gather_t2n4_pairs, grid, block, 0, st, a);
-        else hipLaunchKernelGGL(k_gather_t2n4, grid, block, 0, st, a);
+        else if (!contig) hipLaunchKernelGGL((k_gather_t2n4<false, 2, 16>), g2, block, 0, st, a);
+        else if (wx == 8) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 8>), g2, block, 0, st, a);
+        else if (wx == 32) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 32>), g2, block, 0, st, a);
+        else if (wx == 64) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 64>), g2, block, 0, st, a);
+        else hipLaunchKernelGGL((k_gather_t2n4<true, 2, 16>), g2, block, 0, st, a);
     } else {
         if (fp64) hipLaunchKernelGGL((k_gather_real_generic<double>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((k_gather_real_generic<int64_t>), grid, block, 0, st, a);

@@ -98,20 +98,20 @@ def test_entry_points_validate_before_launch():
     NULL = None
     # pitch < W
     r = L.bsf_filter_varying(ctypes.byref(cfg), bsf.F32, ctypes.c_void_p(16), 8, 8, 4, ctypes.c_void_p(16),
-                             ctypes.c_void_p(16), NULL, NULL, NULL, ctypes.c_void_p(16), 1 << 30, NULL)
+                             ctypes.c_void_p(16), NULL, NULL, NULL, NULL, ctypes.c_void_p(16), 1 << 30, NULL)
     assert r == bsf.E_INVALID
     # workspace too small
     r = L.bsf_filter_varying(ctypes.byref(cfg), bsf.F32, ctypes.c_void_p(16), 8, 8, 8, ctypes.c_void_p(16),
-                             ctypes.c_void_p(16), NULL, NULL, NULL, ctypes.c_void_p(16), 16, NULL)
+                             ctypes.c_void_p(16), NULL, NULL, NULL, NULL, ctypes.c_void_p(16), 16, NULL)
     assert r == bsf.E_WORKSPACE
     # bad dtype
     r = L.bsf_filter_varying(ctypes.byref(cfg), 9, ctypes.c_void_p(16), 8, 8, 8, ctypes.c_void_p(16),
-                             ctypes.c_void_p(16), NULL, NULL, NULL, ctypes.c_void_p(16), 1 << 30, NULL)
+                             ctypes.c_void_p(16), NULL, NULL, NULL, NULL, ctypes.c_void_p(16), 1 << 30, NULL)
     assert r == bsf.E_INVALID
     # numerator output only in integer mode
     r = L.bsf_filter_varying(ctypes.byref(cfg), bsf.U8, ctypes.c_void_p(16), 8, 8, 8, ctypes.c_void_p(16),
-                             ctypes.c_void_p(16), ctypes.c_void_p(16), NULL, NULL, ctypes.c_void_p(16), 1 << 30,
-                             NULL)
+                             ctypes.c_void_p(16), ctypes.c_void_p(16), NULL, NULL, NULL, ctypes.c_void_p(16),
+                             1 << 30, NULL)
     assert r == bsf.E_INVALID
     # preintegrate: F out of range, null G
     r = L.bsf_preintegrate(ctypes.byref(cfg), bsf.F32, ctypes.c_void_p(16), 8, 8, 8, 63, ctypes.c_void_p(16),
@@ -121,4 +121,20 @@ def test_entry_points_validate_before_launch():
                            ctypes.c_void_p(16), 1 << 30, NULL)
     assert r == bsf.E_INVALID
     r = L.bsf_workspace_init(ctypes.c_void_p(16), 8, NULL)
+    assert r == bsf.E_WORKSPACE
+    # derivative output only with continuous steps
+    icfg = bsf.Config(mode=bsf.STEPS_INT).c()
+    r = L.bsf_filter_varying(ctypes.byref(icfg), bsf.F32, ctypes.c_void_p(16), 8, 8, 8, ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), NULL, NULL, ctypes.c_void_p(16), NULL, ctypes.c_void_p(16),
+                             1 << 30, NULL)
+    assert r == bsf.E_INVALID
+    # backward: step gradient needs the saved derivative; integer steps are not differentiable
+    r = L.bsf_filter_backward(ctypes.byref(cfg), 8, 8, ctypes.c_void_p(16), ctypes.c_void_p(16), NULL, NULL,
+                              ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30, NULL)
+    assert r == bsf.E_INVALID
+    r = L.bsf_filter_backward(ctypes.byref(icfg), 8, 8, ctypes.c_void_p(16), ctypes.c_void_p(16), NULL,
+                              ctypes.c_void_p(16), NULL, ctypes.c_void_p(16), 1 << 30, NULL)
+    assert r == bsf.E_UNSUPPORTED
+    r = L.bsf_filter_backward(ctypes.byref(cfg), 8, 8, ctypes.c_void_p(16), ctypes.c_void_p(16), NULL,
+                              ctypes.c_void_p(16), NULL, ctypes.c_void_p(16), 64, NULL)
     assert r == bsf.E_WORKSPACE

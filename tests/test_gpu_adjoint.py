@@ -1,0 +1,164 @@
+"""GPU parity of the adjoint: gradients with respect to the steps (the
+forward's own derivative output times the upstream gradient) and with respect
+to the image (fixed-point scatter of the transposed taps, then transposed
+running sums), against the FP64 oracle, the dot-product identity, torch
+autograd, and central finite differences on the 64x64 crop of the
+differentiation workload."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1109_5114_amd as bsf
+import workloads as WL
+from tests.gpu_util import note
+
+pytestmark = pytest.mark.gpu
+
+DIRS4 = ((1, 0), (0, 1), (1, 1), (1, -1))
+
+
+def case(shape, planes, lo, hi, seed, smooth=False):
+    rng = np.random.default_rng(seed)
+    img = rng.random(shape, dtype=np.float32)
+    if smooth:
+        steps = np.stack([WL.smooth(rng, *shape, lo, hi) for _ in range(planes)]).astype(np.float32)
+    else:
+        steps = rng.uniform(lo, hi, size=(planes,) + shape).astype(np.float32)
+    g = rng.standard_normal(shape).astype(np.float32)
+    return img, steps, g
+
+
+def gpu_grads(cfg, img, steps, g):
+    dev = torch.device("cuda:0")
+    ti, ts, tg = (torch.from_numpy(a).to(dev) for a in (img, steps, g))
+    ds = torch.empty_like(ts)
+    out = bsf.filter_varying(cfg, ti, ts, dsteps=ds)
+    gi, gs = bsf.filter_backward(cfg, ts, tg, dsteps=ds)
+    return out.cpu().numpy(), gi.cpu().numpy(), gs.cpu().numpy(), ds.cpu().numpy()
+
+
+def assert_grad_close(got, ref, rel_norm=1e-6, rel_max=1e-5, what=""):
+    got = got.astype(np.float64)
+    err = np.abs(got - ref)
+    scale = max(np.abs(ref).max(), 1e-30)
+    nrm = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+    assert nrm <= rel_norm, "%s: normwise %.3g" % (what, nrm)
+    assert err.max() <= rel_max * scale, "%s: max %.3g of %.3g" % (what, err.max(), scale)
+    return nrm
+
+
+@pytest.mark.parametrize("order,tied,shape,hi,smooth", [
+    (2, True, (40, 46), 9.0, False),     # tied order-2 four-direction kernels
+    (2, True, (33, 37), 14.0, True),
+    (1, True, (30, 34), 7.0, False),     # generic kernels, order 1
+    (2, False, (11, 13), 3.5, False),    # generic kernels, untied order 2
+])
+def test_gradients_match_oracle(order, tied, shape, hi, smooth):
+    note("adjoint", order, tied, shape)
+    planes = 4 if tied else 4 * order
+    img, steps, g = case(shape, planes, 1.0, hi, 31 + order, smooth)
+    cfg = bsf.Config(order=order, tied=tied, max_step=hi)
+    out, gi, gs, ds = gpu_grads(cfg, img, steps, g)
+    rgi, rgs = O.grad_real(img, DIRS4, order, tied, steps, g)
+    assert_grad_close(gi, rgi, what="grad_img")
+    # right derivative at kinks on both sides; a step whose phase sits within
+    # float rounding of a kink can take the other one-sided value
+    assert_grad_close(gs, rgs, what="grad_steps")
+
+
+def test_dot_product_identity_on_gpu():
+    """<K f, g> = <f, K^T g> with the GPU forward and the GPU adjoint."""
+    note("dot product")
+    img, steps, g = case((64, 70), 4, 1.0, 16.0, 41, smooth=True)
+    cfg = bsf.Config(order=2, max_step=16.0)
+    out, gi, _, _ = gpu_grads(cfg, img, steps, g)
+    lhs = float((out.astype(np.float64) * g).sum())
+    rhs = float((img.astype(np.float64) * gi).sum())
+    assert abs(lhs - rhs) <= 1e-6 * (np.abs(out * g).sum())
+
+
+def test_autograd_function():
+    note("autograd")
+    img, steps, g = case((36, 40), 4, 1.0, 10.0, 43)
+    cfg = bsf.Config(order=2, max_step=10.0)
+    dev = torch.device("cuda:0")
+    ti = torch.from_numpy(img).to(dev).requires_grad_(True)
+    ts = torch.from_numpy(steps).to(dev).requires_grad_(True)
+    out = bsf.filter(ti, ts, cfg)
+    out.backward(torch.from_numpy(g).to(dev))
+    _, gi, gs, _ = gpu_grads(cfg, img, steps, g)
+    np.testing.assert_array_equal(ti.grad.cpu().numpy(), gi)
+    np.testing.assert_array_equal(ts.grad.cpu().numpy(), gs)
+    # image only: the steps' derivative is not computed
+    ti.grad = None
+    ts2 = torch.from_numpy(steps).to(dev)
+    bsf.filter(ti, ts2, cfg).backward(torch.from_numpy(g).to(dev))
+    np.testing.assert_array_equal(ti.grad.cpu().numpy(), gi)
+
+
+def test_zero_upstream_gradient():
+    note("zero gout")
+    img, steps, _ = case((20, 22), 4, 1.0, 6.0, 45)
+    cfg = bsf.Config(order=2, max_step=6.0)
+    _, gi, gs, _ = gpu_grads(cfg, img, steps, np.zeros((20, 22), np.float32))
+    assert not gi.any() and not gs.any()
+
+
+@pytest.mark.slow
+def test_differentiation_workload_crop_finite_differences():
+    """Image 0 of the differentiation workload (1024^2, steps in [1.5, 20]):
+    the step gradient on the 64x64 crop against FP64 central differences of
+    the oracle (h = 1e-3; entries within 2h of a phase kink masked) and against
+    the oracle's analytic gradient; the image gradient on the crop against the
+    oracle's adjoint."""
+    note("fd crop 1024")
+    d = WL.workload5(B=1)
+    img, steps, g = d["imgs"][0], d["steps"][0], d["gout"][0]
+    y0, y1, x0, x1 = d["fd_crop"]
+    cfg = bsf.Config(order=2, max_step=20.0)
+    out, gi, gs, ds = gpu_grads(cfg, img, steps, g)
+    H, W = img.shape
+    ys, xs = np.mgrid[y0:y1, x0:x1]
+    pix = (ys * W + xs).reshape(-1)
+    # analytic oracle gradient on the crop
+    _, rgs = O.grad_real(img, DIRS4, 2, True, steps, g, pix=pix, want_img=False)
+    got = gs.reshape(4, -1)[:, pix].T
+    assert_grad_close(got, rgs, what="grad_steps crop")
+    # central differences: out at one pixel depends only on its own steps
+    h = 1e-3
+    rng = np.random.default_rng(47)
+    sel = rng.choice(len(pix), 96, replace=False)
+    fd, an = [], []
+    for n in sel:
+        p = int(pix[n])
+        y, x = divmod(p, W)
+        for q in range(4):
+            s0 = float(steps[q, y, x])
+            if abs((s0 - 1) / 2 - round((s0 - 1) / 2)) * 2 < 2 * h:
+                continue
+            vals = []
+            for sgn in (1, -1):
+                sv = [float(steps[k, y, x]) for k in range(4)]
+                sv[q] = s0 + sgn * h
+                kx0, ky0, K = O.kernel_real([u for u in DIRS4 for _ in range(2)], [v for v in sv for _ in range(2)])
+                kh, kw = K.shape
+                acc = 0.0
+                for b in range(kh):
+                    yy = y + ky0 + b
+                    if 0 <= yy < H:
+                        xa, xb = max(0, x + kx0), min(W, x + kx0 + kw)
+                        acc += float((K[b, xa - (x + kx0):xb - (x + kx0)] * img[yy, xa:xb]).sum())
+                vals.append(acc)
+            fd.append(float(g[y, x]) * (vals[0] - vals[1]) / (2 * h))
+            an.append(float(gs[q, y, x]))
+    fd, an = np.array(fd), np.array(an)
+    assert len(fd) > 300
+    assert np.abs(fd - an).max() <= 1e-4 * max(1.0, np.abs(fd).max())
+    # image gradient on the crop: every output pixel whose footprint can reach
+    # the crop contributes (reach < 2 * 11 * 3 + 8 = 74 px)
+    m = 74
+    rgi, _ = O.grad_real(img, DIRS4, 2, True, steps, g,
+                         window=(max(0, x0 - m), min(W, x1 + m), max(0, y0 - m), min(H, y1 + m)),
+                         want_steps=False)
+    assert_grad_close(gi[y0:y1, x0:x1], rgi[y0:y1, x0:x1], what="grad_img crop")
