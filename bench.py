@@ -23,8 +23,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpixels/s and HBM GB/s, fwd and fwd+adjoint, 4096^2 N=4 order-2 vs plain path"
 HBM_PEAK_GBS = 8000.0
-# one int64 add per lane per clock: 256 CUs x 64 lanes x 2.4 GHz
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# int64 adds per second: 256 CUs x 64 lanes x 2.4 GHz 32-bit VALU operations,
+# two of which (add, add-with-carry) make one 64-bit add
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
 # exact separable contraction of the 9^4 taps of one pixel: 729 + 243 + 81 + 27
 # groups of nine values reduced to three operator outputs, 8 int64 adds each
 INT64_OPS_PER_PIXEL = (729 + 243 + 81 + 27) * 8
@@ -44,6 +45,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-pixels", type=int, default=48)
+    ap.add_argument("--adjoint-steps", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=64, help="images in the batched workload (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the filter would shard by "
@@ -54,6 +59,7 @@ def main():
     import torch
 
     import paper_1109_5114_amd as bsf
+    import paper_1109_5114_amd.tune as tuner
     import workloads as WL
 
     dev = torch.device("cuda:0")
@@ -64,6 +70,11 @@ def main():
     cfg = bsf.Config(dirs=d["dirs"], order=2, tied=True, mode=bsf.STEPS_REAL, max_step=d["max_step"])
     img = torch.from_numpy(d["img"]).to(dev)
     steps = torch.from_numpy(d["steps"]).to(dev)
+    tuning = None
+    if not args.no_tune:
+        t = time.time()
+        tuning = tuner.tune(cfg, H, W, dev)
+        log("tuned in %.1f s: gather_wx %d line_tl %d" % (time.time() - t, tuning["gather_wx"], tuning["line_tl"]))
     geo = bsf.plan(cfg, H, W)
     ws = bsf.Workspace(geo.workspace_bytes, dev)
     out = torch.empty((H, W), dtype=torch.float32, device=dev)
@@ -128,6 +139,101 @@ def main():
     plain_rel = float(np.max(np.abs(got64 - ref) / np.maximum(np.abs(ref), 2.0 ** -10)))
     log("plain fp64 %.3f ms, max abs err %.3g" % (plain_ms, plain_abs))
 
+    # ---- forward + adjoint (image and step gradients) on the same workload
+    fa = None
+    if args.adjoint_steps > 0:
+        gen = np.random.default_rng(11095114 + 99)
+        gout = torch.from_numpy(gen.standard_normal((H, W), dtype=np.float32)).to(dev)
+        ds = torch.empty_like(steps)
+        gi = torch.empty_like(out)
+        gs = torch.empty_like(steps)
+        wsb = bsf.Workspace(bsf.backward_workspace_bytes(cfg, H, W), dev)
+
+        def bwd():
+            bsf.filter_backward(cfg, steps, gout, dsteps=ds, ws=wsb, grad_img=gi, grad_steps=gs)
+
+        def fwd_adj():
+            bsf.forward_prepare(cfg, img, steps, ws)
+            bsf.forward_apply(cfg, bsf.F32, steps, ws, out, dsteps=ds)
+            bwd()
+
+        fwd_adj()
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        fwd_ms, bwd_ms = [], []
+        for _ in range(args.adjoint_steps):
+            e0.record(stream)
+            bsf.forward_prepare(cfg, img, steps, ws)
+            bsf.forward_apply(cfg, bsf.F32, steps, ws, out, dsteps=ds)
+            e1.record(stream)
+            bwd()
+            e2.record(stream)
+            torch.cuda.synchronize()
+            fwd_ms.append(e0.elapsed_time(e1))
+            bwd_ms.append(e1.elapsed_time(e2))
+        # step-gradient spot check against the oracle's analytic derivative
+        sub = pix[:16]
+        _, rgs = O.grad_real(d["img"], d["dirs"], 2, True, d["steps"], gout.cpu().numpy(), pix=sub,
+                             want_img=False)
+        ggs = gs.cpu().numpy().reshape(4, -1)[:, sub].T
+        gerr = float(np.max(np.abs(ggs - rgs)) / max(np.abs(rgs).max(), 1e-30))
+        t_fa = float(np.mean(fwd_ms) + np.mean(bwd_ms))
+        fa = {"ms_per_step": t_fa, "value": H * W / (t_fa / 1e3) / 1e6, "unit": "Mpixels/s",
+              "forward_with_derivative_ms": float(np.mean(fwd_ms)), "backward_ms": float(np.mean(bwd_ms)),
+              "steps": args.adjoint_steps, "grad_steps_max_rel_err_vs_oracle": gerr}
+        log("fwd+adjoint %.3f ms (fwd %.3f, bwd %.3f)" % (t_fa, np.mean(fwd_ms), np.mean(bwd_ms)))
+
+    # ---- batched: images of uneven sizes, each stage one launch over the batch, replayed as a graph
+    batched = None
+    if args.batch > 0:
+        del ws64, out64
+        t = time.time()
+        d4 = WL.workload4(B=args.batch)
+        log("batched inputs generated in %.1f s" % (time.time() - t))
+        cfg4 = bsf.Config(dirs=d4["dirs"], order=2, tied=True, mode=bsf.STEPS_REAL, max_step=d4["max_step"])
+        px = [it["img"].size for it in d4["items"]]
+        side = int(math.sqrt(sum(px) / len(px)))
+        tuning4 = None if args.no_tune else tuner.tune(cfg4, side, side, dev)
+        imgs4 = [torch.from_numpy(it["img"]).to(dev) for it in d4["items"]]
+        steps4 = [torch.from_numpy(it["steps"]).to(dev) for it in d4["items"]]
+        batch = bsf.Batch(cfg4, imgs4, steps4)
+        batch.run(use_graph=True)                       # records the graph
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.batch_steps):
+            batch.run(use_graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        b_ms = e0.elapsed_time(e1) / args.batch_steps
+        bflags, bF, _ = batch.ws.status()
+        # the same images one call each, for context
+        wsi = bsf.Workspace(max(bsf.plan(cfg4, *im.shape).workspace_bytes for im in imgs4), dev)
+        e0.record(stream)
+        for im, st, o in zip(imgs4, steps4, batch.outs):
+            bsf.filter_varying(cfg4, im, st, out=o, ws=wsi)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        loop_ms = e0.elapsed_time(e1)
+        # oracle spot check on sampled pixels of a few images
+        berr = 0.0
+        for b in range(0, len(imgs4), max(1, len(imgs4) // 4)):
+            it = d4["items"][b]
+            hh, ww = it["img"].shape
+            pb = rng.integers(0, hh * ww, 8)
+            refb = O.filter(it["img"], d4["dirs"], 2, True, O.REAL, it["steps"], pix=pb)
+            gotb = batch.outs[b].cpu().numpy().reshape(-1)[pb].astype(np.float64)
+            berr = max(berr, float(np.max(np.abs(gotb - refb) / np.maximum(np.abs(refb), 2.0 ** -10))))
+        batched = {"value": sum(px) / (b_ms / 1e3) / 1e6, "unit": "Mpixels/s", "ms_per_step": b_ms,
+                   "images": len(px), "pixels": int(sum(px)), "graph": True, "steps": args.batch_steps,
+                   "per_image_calls_ms": loop_ms, "frac_bits": bF, "device_flags": bflags,
+                   "max_rel_err_vs_oracle": berr,
+                   "tuning": None if tuning4 is None else {k: tuning4[k] for k in ("gather_wx", "line_tl")},
+                   "workload": d4["name"]}
+        log("batched %d images %.1f Mpx: %.3f ms (per-image calls %.3f ms)" % (len(px), sum(px) / 1e6, b_ms,
+                                                                                loop_ms))
+        del batch, imgs4, steps4, wsi
+
     # ---- CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -174,7 +280,9 @@ def main():
                      "pixels_checked": int(len(pix)), "frac_bits": F, "device_flags": flags},
         "plain_fp64": {"ms_per_step": plain_ms, "value": H * W / (plain_ms / 1e3) / 1e6,
                        "max_abs_err_vs_oracle": plain_abs, "max_rel_err_vs_oracle": plain_rel},
-        "fwd_adjoint": None,
+        "fwd_adjoint": fa,
+        "batched": batched,
+        "tuning": None if tuning is None else {k: tuning[k] for k in ("gather_wx", "line_tl")},
     }
     print(json.dumps(res))
 

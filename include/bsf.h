@@ -202,8 +202,8 @@ bsf_status bsf_forward_apply(const bsf_config *cfg, bsf_dtype dtype, int64_t H, 
                              void *stream);
 
 /*
- * Adjoint of the forward filter with continuous steps (north-star
- * differentiation).  Given the upstream gradient gout [H][W] of a scalar loss L:
+ * Adjoint of the forward filter with continuous steps (differentiation of a
+ * loss through the filter).  Given the upstream gradient gout [H][W] of a scalar loss L:
  *   grad_img   [H][W]          dL/df = K^T gout (nullable), computed as the scatter
  *                              of the pixel's tap patterns weighted in fixed point
  *                              by gout / prod s times the phase products, followed
@@ -222,10 +222,25 @@ bsf_status bsf_filter_backward(const bsf_config *cfg, int64_t H, int64_t W, cons
 
 /*
  * Batched forward over B images of uneven sizes (FP32 images, one shared
- * configuration).  descs is a host array.  Every image's work is enqueued on
- * `stream`; ws must hold bsf_batched_workspace_bytes.  use_graph = 1 captures
- * the launches into a HIP graph once per (workspace, descriptor set) and
- * replays it.
+ * configuration; the forward of bsf_filter_varying applied to each image, with
+ * results identical to B separate calls).  descs is a host array of B entries:
+ * img FP32 [H][pitch], steps FP32 [planes][H][W], out FP32 [H][W], all device
+ * pointers owned by the caller; H = 0 or W = 0 skips an entry.  Each stage of
+ * the path is one launch over the whole batch (a work list of (image, tile)
+ * items), so small images do not leave the device idle.
+ *
+ * ws (device, >= bsf_batched_workspace_bytes for the same cfg and descs, and
+ * the same tuning) holds a batch status block at its start (read with
+ * bsf_read_device_status: flags OR-ed over the images, F_used the smallest F,
+ * log2_bound the largest), the launch tables, and one single-image workspace
+ * per image.  use_graph = 1 on a non-NULL stream that is not already capturing
+ * records the launches into a HIP graph on the first call for a (device, cfg,
+ * descs, ws, tuning) key and replays it on later calls with the same key
+ * (a process-wide cache of up to 16 graphs, least recently used evicted);
+ * otherwise the launches are enqueued directly.  Errors: BSF_E_INVALID for a
+ * bad cfg, B < 0 or > 65536, a NULL pointer or pitch < W; BSF_E_WORKSPACE
+ * when ws is too small; BSF_E_DEVICE when a launch or the capture fails.
+ * bsf_batched_workspace_bytes returns 0 for invalid arguments.
  */
 typedef struct {
     const float *img;
@@ -237,6 +252,20 @@ typedef struct {
 size_t bsf_batched_workspace_bytes(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs);
 bsf_status bsf_filter_batched(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs,
                               void *ws, size_t ws_bytes, void *stream, int32_t use_graph);
+
+/*
+ * Launch shapes (process-wide; set them before sizing workspaces and
+ * launching work, not concurrently with other calls):
+ *   gather_wx  width in pixels of one wavefront's block in the tied order-2
+ *              four-direction gather: 8, 16, 32 or 64 (default 16);
+ *   line_tl    steps per tile of the sheared running sums: a power of two in
+ *              [16, 4096] (default 64).  Workspace sizes depend on it.
+ * The result of every call is the same for every setting; only its speed
+ * differs.  bsf_set_tuning returns BSF_E_INVALID for other values and keeps
+ * the current ones; bsf_get_tuning writes the current values (NULL skips).
+ */
+bsf_status bsf_set_tuning(int32_t gather_wx, int32_t line_tl);
+void bsf_get_tuning(int32_t *gather_wx, int32_t *line_tl);
 
 /*
  * Synchronises `stream`, then copies the status word from the workspace

@@ -54,7 +54,8 @@ _lib = None
 EXPORTS = ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_varying",
            "bsf_forward_prepare", "bsf_forward_apply",
            "bsf_backward_workspace_bytes", "bsf_filter_backward", "bsf_batched_workspace_bytes",
-           "bsf_filter_batched", "bsf_read_device_status", "bsf_status_string", "bsf_version")
+           "bsf_filter_batched", "bsf_set_tuning", "bsf_get_tuning", "bsf_read_device_status",
+           "bsf_status_string", "bsf_version")
 
 
 def lib():
@@ -79,6 +80,9 @@ def lib():
         L.bsf_batched_workspace_bytes.argtypes = [cfgp, i32, ctypes.POINTER(_ImageDesc)]
         L.bsf_batched_workspace_bytes.restype = sz
         L.bsf_filter_batched.argtypes = [cfgp, i32, ctypes.POINTER(_ImageDesc), P, sz, P, i32]
+        L.bsf_set_tuning.argtypes = [i32, i32]
+        L.bsf_get_tuning.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.bsf_get_tuning.restype = None
         L.bsf_read_device_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
         L.bsf_status_string.argtypes = [i32]
@@ -86,7 +90,8 @@ def lib():
         L.bsf_version.restype = ctypes.c_char_p
         for name in ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_varying",
                      "bsf_forward_prepare", "bsf_forward_apply",
-                     "bsf_filter_backward", "bsf_filter_batched", "bsf_read_device_status"):
+                     "bsf_filter_backward", "bsf_filter_batched", "bsf_set_tuning",
+                     "bsf_read_device_status"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -202,8 +207,12 @@ def _workspace(device, nbytes):
 def _check_image(img):
     if not img.is_cuda or img.dim() != 2:
         raise ValueError("image must be a 2-D device tensor")
-    if img.stride(1) != 1:
+    if img.numel() and img.stride(1) != 1:
         raise ValueError("image rows must be contiguous")
+
+
+def _pitch(img):
+    return img.stride(0) if img.numel() else img.shape[1]
 
 
 def _check_steps(cfg, steps, H, W):
@@ -222,7 +231,7 @@ def preintegrate(cfg: Config, img: torch.Tensor, F: int = 24, ws: Optional[Works
     G = torch.empty((g.win_h, g.win_w), dtype=dt, device=img.device)
     ws = ws or _workspace(img.device, g.workspace_bytes_g_external)
     ws.ensure(g.workspace_bytes_g_external)
-    _check(lib().bsf_preintegrate(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, img.stride(0),
+    _check(lib().bsf_preintegrate(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, _pitch(img),
                                   int(F), _ptr(G), ws.ptr(), ws.nbytes, _stream(img.device)),
            "bsf_preintegrate")
     return G
@@ -252,7 +261,7 @@ def filter_varying(cfg: Config, img: torch.Tensor, steps: torch.Tensor, out: Opt
     ws.ensure(need)
     if dsteps is not None:
         _check_steps(cfg, dsteps, H, W)
-    _check(lib().bsf_filter_varying(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, img.stride(0),
+    _check(lib().bsf_filter_varying(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, _pitch(img),
                                     _ptr(steps), _ptr(out), _ptr(num), _ptr(den), _ptr(dsteps), _ptr(G), ws.ptr(),
                                     ws.nbytes, _stream(dev)),
            "bsf_filter_varying")
@@ -272,7 +281,7 @@ def forward_prepare(cfg: Config, img: torch.Tensor, steps: torch.Tensor, ws: Wor
     _check_image(img)
     H, W = img.shape
     _check_steps(cfg, steps, H, W)
-    _check(lib().bsf_forward_prepare(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, img.stride(0),
+    _check(lib().bsf_forward_prepare(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, _pitch(img),
                                      _ptr(steps), _ptr(G), ws.ptr(), ws.nbytes, _stream(img.device)),
            "bsf_forward_prepare")
 
@@ -289,24 +298,102 @@ def forward_apply(cfg: Config, dtype_code: int, steps: torch.Tensor, ws: Workspa
     return out
 
 
+def backward_workspace_bytes(cfg: Config, H: int, W: int) -> int:
+    n = lib().bsf_backward_workspace_bytes(ctypes.byref(cfg.c()), int(H), int(W))
+    if n == 0:
+        raise BsfError(E_INVALID, "bsf_backward_workspace_bytes")
+    return n
+
+
 def filter_backward(cfg: Config, steps: torch.Tensor, gout: torch.Tensor, dsteps: Optional[torch.Tensor] = None,
-                    want_img: bool = True, want_steps: bool = True, ws: Optional[Workspace] = None):
+                    want_img: bool = True, want_steps: bool = True, ws: Optional[Workspace] = None,
+                    grad_img: Optional[torch.Tensor] = None, grad_steps: Optional[torch.Tensor] = None):
     """Adjoint: returns (grad_img or None, grad_steps or None).  grad_steps
-    needs dsteps (d out / d steps from the forward call)."""
+    needs dsteps (d out / d steps from the forward call).  Output tensors may
+    be passed in (grad_img / grad_steps); otherwise they are allocated."""
     _, H, W = steps.shape
     _check_steps(cfg, steps, H, W)
     if gout.dtype != torch.float32 or not gout.is_contiguous() or tuple(gout.shape) != (H, W):
         raise ValueError("gout must be a contiguous float32 [H][W] device tensor")
     dev = steps.device
-    gi = torch.empty((H, W), dtype=torch.float32, device=dev) if want_img else None
-    gs = torch.empty_like(steps) if want_steps else None
-    need = lib().bsf_backward_workspace_bytes(ctypes.byref(cfg.c()), H, W)
+    gi = gs = None
+    if want_img:
+        gi = grad_img if grad_img is not None else torch.empty((H, W), dtype=torch.float32, device=dev)
+        if gi.dtype != torch.float32 or not gi.is_contiguous() or tuple(gi.shape) != (H, W):
+            raise ValueError("grad_img must be a contiguous float32 [H][W] device tensor")
+    if want_steps:
+        gs = grad_steps if grad_steps is not None else torch.empty_like(steps)
+        _check_steps(cfg, gs, H, W)
+    need = backward_workspace_bytes(cfg, H, W)
     ws = ws or _workspace(dev, need)
     ws.ensure(need)
     _check(lib().bsf_filter_backward(ctypes.byref(cfg.c()), H, W, _ptr(steps), _ptr(gout), _ptr(dsteps), _ptr(gi),
                                      _ptr(gs), ws.ptr(), ws.nbytes, _stream(dev)),
            "bsf_filter_backward")
     return gi, gs
+
+
+def set_tuning(gather_wx: int, line_tl: int):
+    """Launch shapes of the tied order-2 gather and the sheared running sums
+    (process-wide; results do not depend on them)."""
+    _check(lib().bsf_set_tuning(int(gather_wx), int(line_tl)), "bsf_set_tuning")
+
+
+def get_tuning() -> Tuple[int, int]:
+    wx, tl = ctypes.c_int32(), ctypes.c_int32()
+    lib().bsf_get_tuning(ctypes.byref(wx), ctypes.byref(tl))
+    return wx.value, tl.value
+
+
+class Batch:
+    """A fixed set of FP32 images, step fields and outputs filtered together
+    by bsf_filter_batched.  The descriptors and the workspace stay the same
+    between runs, so with use_graph the launches are recorded once and
+    replayed."""
+
+    def __init__(self, cfg: Config, imgs: Sequence[torch.Tensor], steps: Sequence[torch.Tensor],
+                 outs: Optional[Sequence[torch.Tensor]] = None):
+        if len(imgs) != len(steps):
+            raise ValueError("one step field per image")
+        self.cfg = cfg
+        self.imgs, self.steps = list(imgs), list(steps)
+        dev = self.imgs[0].device if self.imgs else torch.device("cuda")
+        for im, st in zip(self.imgs, self.steps):
+            _check_image(im)
+            if im.dtype != torch.float32:
+                raise TypeError("batched images are float32")
+            _check_steps(cfg, st, *im.shape)
+        if outs is None:
+            outs = [torch.empty(tuple(im.shape), dtype=torch.float32, device=dev) for im in self.imgs]
+        self.outs = list(outs)
+        for im, o in zip(self.imgs, self.outs):
+            if o.dtype != torch.float32 or not o.is_contiguous() or o.shape != im.shape:
+                raise ValueError("outputs are contiguous float32 tensors of the images' shapes")
+        B = len(self.imgs)
+        self.descs = (_ImageDesc * max(B, 1))()
+        for b, (im, st, o) in enumerate(zip(self.imgs, self.steps, self.outs)):
+            d = self.descs[b]
+            d.img, d.steps, d.out = im.data_ptr(), st.data_ptr(), o.data_ptr()
+            d.H, d.W = im.shape[0], im.shape[1]
+            d.pitch = _pitch(im)
+        self.B = B
+        self._cfg_c = cfg.c()
+        need = lib().bsf_batched_workspace_bytes(ctypes.byref(self._cfg_c), B, self.descs)
+        if need == 0:
+            raise BsfError(E_INVALID, "bsf_batched_workspace_bytes")
+        self.ws = Workspace(need, dev)
+
+    def run(self, use_graph: bool = True):
+        _check(lib().bsf_filter_batched(ctypes.byref(self._cfg_c), self.B, self.descs, self.ws.ptr(),
+                                        self.ws.nbytes, _stream(self.ws.buf.device), int(bool(use_graph))),
+               "bsf_filter_batched")
+        return self.outs
+
+
+def filter_batched(cfg: Config, imgs: Sequence[torch.Tensor], steps: Sequence[torch.Tensor],
+                   use_graph: bool = False):
+    """One-shot batched forward; returns the list of outputs."""
+    return Batch(cfg, imgs, steps).run(use_graph)
 
 
 class _Filter(torch.autograd.Function):

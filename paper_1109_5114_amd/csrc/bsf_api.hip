@@ -108,9 +108,10 @@ bsf_status make_plan(const bsf_config *cfg, int64_t H, int64_t W, Plan *p) {
 
 }  // namespace bsf
 
-using namespace bsf;
+namespace bsf {
 
-namespace {
+Tuning g_tuning{16, 64};
+const Tuning &tuning() { return g_tuning; }
 
 size_t ws_bytes_for(const Plan &p, bool g_internal) {
     return kStatusBytes + (g_internal ? align_up(p.g_bytes) : 0) + p.scan_aux_bytes;
@@ -161,7 +162,9 @@ GatherArgs gather_args(const Plan &p, const void *G, const float *steps, float *
     return a;
 }
 
-}  // namespace
+}  // namespace bsf
+
+using namespace bsf;
 
 extern "C" {
 
@@ -358,17 +361,17 @@ bsf_status bsf_filter_backward(const bsf_config *cfg, int64_t H, int64_t W, cons
                               grad_steps, st);
 }
 
-size_t bsf_batched_workspace_bytes(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs) {
-    (void)cfg;
-    (void)B;
-    (void)descs;
-    return 0;
+bsf_status bsf_set_tuning(int32_t gather_wx, int32_t line_tl) {
+    if (gather_wx != 8 && gather_wx != 16 && gather_wx != 32 && gather_wx != 64) return BSF_E_INVALID;
+    if (line_tl < 16 || line_tl > 4096 || (line_tl & (line_tl - 1)) != 0) return BSF_E_INVALID;
+    g_tuning.gather_wx = gather_wx;
+    g_tuning.line_tl = line_tl;
+    return BSF_OK;
 }
 
-bsf_status bsf_filter_batched(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs, void *ws,
-                              size_t ws_bytes, void *stream, int32_t use_graph) {
-    (void)cfg; (void)B; (void)descs; (void)ws; (void)ws_bytes; (void)stream; (void)use_graph;
-    return BSF_E_UNSUPPORTED;
+void bsf_get_tuning(int32_t *gather_wx, int32_t *line_tl) {
+    if (gather_wx) *gather_wx = g_tuning.gather_wx;
+    if (line_tl) *line_tl = g_tuning.line_tl;
 }
 
 bsf_status bsf_read_device_status(void *ws, void *stream, uint32_t *flags, int32_t *F_used, int32_t *log2_bound,

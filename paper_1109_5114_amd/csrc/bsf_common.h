@@ -50,8 +50,53 @@ struct Src {
 
 bsf_status make_plan(const bsf_config *cfg, int64_t H, int64_t W, Plan *p);
 
+// Launch-shape choices (set by the tuner through bsf_set_tuning).
+struct Tuning {
+    int gather_wx;   // width in pixels of the wavefront block of the tied order-2 gather (8, 16, 32, 64)
+    int line_tl;     // steps per line tile of the sheared scans (power of two, 16 .. 4096)
+};
+const Tuning &tuning();
+
+// Sheared line tiles of a running sum along (dx, dy), dy != 0.
+struct LineGeom {
+    int dx, dy, ay, tl;
+    int64_t Hp, Wp;
+    int64_t T;         // steps per residue class (rows / |dy|, rounded up)
+    int64_t c_lo;      // start column of the first line
+    int64_t n_groups;  // groups of 64 lines
+    int64_t n_chunks;  // chunks of tl steps
+};
+LineGeom line_geom(int dx, int dy, int64_t Hp, int64_t Wp, int tl);
+
+// One image's share of a running-sum pass, for batched launches.
+struct ScanJob {
+    void *G;
+    void *aux;
+    const int32_t *status;
+    Src src;
+    LineGeom g;
+    int64_t Hp, Wp;
+    int dir;  // row passes: +1 forward, -1 reversed
+};
+
+// Job b of a batched launch owns the work items [prefix[b], prefix[b+1]).
+__device__ __forceinline__ int find_job(const int64_t *__restrict__ prefix, int B, int64_t item) {
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Running sums on the window (scan.hip).  G is int64 (exact) or double (fp64).
 size_t scan_aux_bytes(const Plan &p);
+// One pass over a batch: jobs and the three work prefixes (rows / tiles /
+// line groups) are device tables; totals are the last prefix entries.
+bsf_status run_pass_batch(int arith, int order, int src_kind, int dx, int dy, const ScanJob *jobs,
+                          const int64_t *prefix_items, int64_t total_items, const int64_t *prefix_groups,
+                          int64_t total_groups, int B, hipStream_t st);
 bsf_status run_preintegrate(const Plan &p, const Src &src, void *G, void *aux, const int32_t *status,
                             hipStream_t st);
 // Reverse (transposed) running sums on the window, last direction first.
@@ -74,6 +119,25 @@ struct GatherArgs {
     int32_t plane[BSF_MAX_FACTORS];  // step plane of factor j
 };
 bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st);
+// Arguments of the gather for one image (bsf_api.hip).
+GatherArgs gather_args(const Plan &p, const void *G, const float *steps, float *out, int64_t *num, int64_t *den,
+                       float *dsteps, const int32_t *status);
+// Single-image workspace: [status][G when internal][scan carries].
+size_t ws_bytes_for(const Plan &p, bool g_internal);
+// Batched gather: table / prefix are device arrays over B images; prefix has
+// the cumulative pixel-tile counts gather_tiles() gives per image.
+int64_t gather_tiles(const Plan &p, const GatherArgs &a);
+// Images with equal variants run the same gather kernel and tile shape.
+int gather_variant(const Plan &p, const GatherArgs &a);
+bsf_status run_gather_batch(const Plan &p0, const GatherArgs &a0, const GatherArgs *table, const int64_t *prefix,
+                            int B, int64_t total_tiles, hipStream_t st);
+// Batched range check / fixed-point choice: jobs are BoundJob records
+// (make_bound_job), prefix the cumulative row counts.
+size_t bound_job_bytes();
+void make_bound_job(const float *steps, const float *img, int64_t H, int64_t W, int64_t pitch, int32_t *status,
+                    void *out);
+bsf_status run_bound_batch(const Plan &p0, int img_kind, int32_t F_request, const void *jobs, const int64_t *prefix,
+                           int B, int64_t total_rows, hipStream_t st);
 
 // Bound / range check and fixed-point choice (gather.hip).
 // prepare: range check, bound and choice of F (recheck = false); apply with

@@ -12,10 +12,10 @@
 // each exact modulo 2^64 and small in magnitude, and only then weighted by the
 // FP64 phase products.
 //
-// Pixel mapping: a 256-thread workgroup covers a 16x16 pixel tile and each
-// wavefront an 8x8 block, so the 64 lanes of one tap read an 8x8 (plus step
-// variation) patch of the window, which stays within a few cache lines per row.
-#include <stdlib.h>
+// Every kernel runs on one image (arguments by value, 2-D grid of pixel
+// tiles) or on a batch (BATCH: a 1-D work list of (image, tile) items, each
+// block looking up its image's arguments).
+#include <string.h>
 
 #include <type_traits>
 
@@ -26,23 +26,46 @@ namespace {
 
 constexpr int kTile = 16;
 
-__device__ __forceinline__ bool pixel_of_thread(int64_t H, int64_t W, int64_t &x, int64_t &y) {
+// This block's image arguments and pixel-tile coordinates.
+template <bool BATCH>
+__device__ __forceinline__ bool tile_of_block(const GatherArgs &one, const GatherArgs *__restrict__ table,
+                                              const int64_t *__restrict__ prefix, int B, int tile_w, int tile_h,
+                                              GatherArgs &a, int64_t &bx, int64_t &by) {
+    if constexpr (BATCH) {
+        const int64_t gi = blockIdx.x;
+        const int b = find_job(prefix, B, gi);
+        a = table[b];
+        const int64_t item = gi - prefix[b];
+        if (item >= prefix[b + 1] - prefix[b]) return false;
+        const int64_t tiles_x = (a.W + tile_w - 1) / tile_w;
+        bx = item % tiles_x;
+        by = item / tiles_x;
+    } else {
+        a = one;
+        bx = blockIdx.x;
+        by = blockIdx.y;
+    }
+    (void)tile_h;
+    return true;
+}
+
+// 16 x 16 tile, each wavefront an 8 x 8 block.
+__device__ __forceinline__ bool pixel_16x16(const GatherArgs &a, int64_t bx, int64_t by, int64_t &x, int64_t &y) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    x = (int64_t)blockIdx.x * kTile + (w & 1) * 8 + (lane & 7);
-    y = (int64_t)blockIdx.y * kTile + (w >> 1) * 8 + (lane >> 3);
-    return x < W && y < H;
+    x = bx * kTile + (w & 1) * 8 + (lane & 7);
+    y = by * kTile + (w >> 1) * 8 + (lane >> 3);
+    return x < a.W && y < a.H;
 }
 
 // Wavefront of WX x (64/WX) pixels; the four wavefronts of a workgroup stack
-// vertically, so the workgroup covers WX x (256/WX).  Wider wavefronts touch
-// fewer rows (cache lines) per tap load.
+// vertically, so the workgroup covers WX x (256/WX).
 template <int WX>
-__device__ __forceinline__ bool pixel_of_thread_wx(int64_t H, int64_t W, int64_t &x, int64_t &y) {
+__device__ __forceinline__ bool pixel_wx(const GatherArgs &a, int64_t bx, int64_t by, int64_t &x, int64_t &y) {
     constexpr int WY = 64 / WX;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    x = (int64_t)blockIdx.x * WX + (lane % WX);
-    y = (int64_t)blockIdx.y * (4 * WY) + w * WY + (lane / WX);
-    return x < W && y < H;
+    x = bx * WX + (lane % WX);
+    y = by * (4 * WY) + w * WY + (lane / WX);
+    return x < a.W && y < a.H;
 }
 
 __device__ __forceinline__ float clamp_step(float s, float max_step) {
@@ -55,13 +78,21 @@ __device__ __forceinline__ double ldexp_neg(double v, int F) { return __builtin_
 // ----------------------------------------------------------------------------
 // Range check and fixed-point bound.
 // ----------------------------------------------------------------------------
-__global__ void k_status_begin(int32_t *status, int32_t F_request, int recheck) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        status[ST_EP_MAX] = 0;
-        if (!recheck) {
-            status[ST_FABS_BITS] = 0;
-            status[ST_F_REQUEST] = F_request;
-        }
+struct BoundJob {
+    const float *steps;
+    const float *img;  // nullable: float image whose max |f| bounds F
+    int64_t H, W, pitch;
+    int32_t *status;
+};
+
+template <bool BATCH>
+__global__ void k_status_begin(BoundJob one, const BoundJob *__restrict__ jobs, int32_t F_request, int recheck) {
+    if (threadIdx.x != 0) return;
+    int32_t *status = BATCH ? jobs[blockIdx.x].status : one.status;
+    status[ST_EP_MAX] = 0;
+    if (!recheck) {
+        status[ST_FABS_BITS] = 0;
+        status[ST_F_REQUEST] = F_request;
     }
 }
 
@@ -72,23 +103,38 @@ __device__ __forceinline__ int ceil_log2(double v) {
     return m == 0.5 ? e - 1 : e;
 }
 
-// One workgroup per group of rows (grid-stride over rows, threads stride over
-// columns), a wavefront and LDS reduction, and one atomic per workgroup.
-__global__ __launch_bounds__(256) void k_bound(const float *__restrict__ steps, int64_t H, int64_t W, int planes,
-                                               int per_plane, int mode, float max_step,
-                                               const float *__restrict__ img, int64_t pitch, int32_t *status) {
+// Rows y = first, first + stride, ...; threads stride over columns; a
+// wavefront and LDS reduction, and one atomic per workgroup.  Single image:
+// one workgroup per group of rows; batch: one workgroup per (image, row).
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_bound(BoundJob one, const BoundJob *__restrict__ jobs,
+                                               const int64_t *__restrict__ prefix, int B, int planes, int per_plane,
+                                               int mode, float max_step) {
     __shared__ int s_ep[4], s_bad[4];
     __shared__ unsigned s_fb[4];
+    BoundJob job;
+    int64_t first, stride;
+    if constexpr (BATCH) {
+        const int64_t gi = blockIdx.x;
+        const int b = find_job(prefix, B, gi);
+        job = jobs[b];
+        first = gi - prefix[b];
+        stride = job.H;
+    } else {
+        job = one;
+        first = blockIdx.x;
+        stride = gridDim.x;
+    }
     int ep_max = 0;
     unsigned fbits = 0;
     int bad = 0;
-    const int64_t HW = H * W;
-    for (int64_t y = blockIdx.x; y < H; y += gridDim.x) {
+    const int64_t H = job.H, W = job.W, HW = H * W;
+    for (int64_t y = first; y < H; y += stride) {
         for (int64_t x = threadIdx.x; x < W; x += blockDim.x) {
             const int64_t i = y * W + x;
             double prod = 1.0;
             for (int q = 0; q < planes; ++q) {
-                const float s = steps[q * HW + i];
+                const float s = job.steps[q * HW + i];
                 if (!(s >= 1.0f) || s > max_step) bad = 1;  // catches NaN
                 const float sc = clamp_step(s, max_step);
                 double len;
@@ -103,8 +149,8 @@ __global__ __launch_bounds__(256) void k_bound(const float *__restrict__ steps, 
             // products of small integers are exact in FP64 up to 2^53; above
             // that round the bound up a little so it stays an upper bound
             ep_max = max(ep_max, ceil_log2(prod * (1.0 + 0x1p-40)));
-            if (img) {
-                const float f = fabsf(img[y * pitch + x]);
+            if (job.img) {
+                const float f = fabsf(job.img[y * job.pitch + x]);
                 if (f == f) fbits = max(fbits, __float_as_uint(f));
             }
         }
@@ -127,15 +173,17 @@ __global__ __launch_bounds__(256) void k_bound(const float *__restrict__ steps, 
             fbits = max(fbits, s_fb[k]);
             bad |= s_bad[k];
         }
-        atomicMax(&status[ST_EP_MAX], ep_max);
-        if (img) atomicMax((unsigned *)&status[ST_FABS_BITS], fbits);
-        if (bad) atomicOr((unsigned *)&status[ST_FLAGS], BSF_FLAG_RANGE);
+        atomicMax(&job.status[ST_EP_MAX], ep_max);
+        if (job.img) atomicMax((unsigned *)&job.status[ST_FABS_BITS], fbits);
+        if (bad) atomicOr((unsigned *)&job.status[ST_FLAGS], BSF_FLAG_RANGE);
     }
 }
 
 // img_kind: SRC_F32, SRC_U8 or SRC_U16; arith: exact or fp64.
-__global__ void k_choose_F(int32_t *status, int img_kind, int arith) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+template <bool BATCH>
+__global__ void k_choose_F(BoundJob one, const BoundJob *__restrict__ jobs, int img_kind, int arith) {
+    if (threadIdx.x != 0) return;
+    int32_t *status = BATCH ? jobs[blockIdx.x].status : one.status;
     const int eP = status[ST_EP_MAX];
     int ef;
     bool zero = false;
@@ -184,10 +232,13 @@ __global__ void k_check_F(int32_t *status) {
 // ----------------------------------------------------------------------------
 // Integer steps: 2^M signed taps (Table 1 signs (-1)^popcount), exact.
 // ----------------------------------------------------------------------------
-template <typename V, int MT>
-__global__ __launch_bounds__(256) void k_gather_int(GatherArgs a) {
-    int64_t x, y;
-    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+template <typename V, int MT, bool BATCH>
+__global__ __launch_bounds__(256) void k_gather_int(GatherArgs one, const GatherArgs *__restrict__ table,
+                                                    const int64_t *__restrict__ prefix, int B) {
+    GatherArgs a;
+    int64_t bx, by, x, y;
+    if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
+    if (!pixel_16x16(a, bx, by, x, y)) return;
     const int M = MT > 0 ? MT : a.M;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
@@ -239,10 +290,13 @@ __global__ __launch_bounds__(256) void k_gather_int(GatherArgs a) {
 // prod_j (e_j ? phi_j : 1 - phi_j).  4^M loads per pixel: the reference path
 // for configurations without a specialised kernel.
 // ----------------------------------------------------------------------------
-template <typename V>
-__global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs a) {
-    int64_t x, y;
-    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+template <typename V, bool BATCH>
+__global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs one, const GatherArgs *__restrict__ table,
+                                                             const int64_t *__restrict__ prefix, int B) {
+    GatherArgs a;
+    int64_t bx, by, x, y;
+    if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
+    if (!pixel_16x16(a, bx, by, x, y)) return;
     const int M = a.M;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
@@ -321,18 +375,8 @@ __global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs a) {
 // The 3^4 = 81 products J[a0][a1][a2][a3] are contracted one direction at a
 // time (innermost first) in exact int64; the innermost direction is the one
 // with window offset +1 when the set has it, so each cluster is three
-// consecutive int64.  The outermost direction's taps are visited in an order
-// that finishes one operator at a time, so only 27 accumulators are live.
+// consecutive int64.
 // ----------------------------------------------------------------------------
-
-// Tap index -> (operator, coefficient) memberships, index order
-// T0 T1 T2 M0 M1 M2 B0 B1 B2.
-__device__ __forceinline__ void offsets9(int32_t R, int32_t off, int32_t o[9]) {
-    const int32_t t = 2 * R * off, m = -2 * off, b = (-2 * R - 4) * off;
-    o[0] = t; o[1] = t + off; o[2] = t + 2 * off;
-    o[3] = m; o[4] = m + off; o[5] = m + 2 * off;
-    o[6] = b; o[7] = b + off; o[8] = b + 2 * off;
-}
 
 // One 8-byte running-sum value.  Offsets are 32-bit byte offsets from the
 // window base (the launcher checks the window is below 4 GiB); forming the
@@ -344,11 +388,9 @@ __device__ __forceinline__ int64_t ldG(const char *__restrict__ p) {
 
 // acc[a1][a2][a3] += sum over the 9 x 9 x 9 taps (p1, p2, p3) of directions
 // 1..3 of C1 C2 C3 G[b + o1(p1) + o2(p2) + o3(p3)], direction 3 innermost.
-// Tap index p = 3 * cluster + sub, clusters T (2R + sub), M (-2 + sub),
-// B (-2R - 4 + sub); per direction the operators are
-//   aa = T0 + B2 - 2 M1,  ab = T1 + B1 - M0 - M2,  bb = T2 + B0 - 2 M1.
-// The two inner levels keep positive and negative parts apart so that every
-// fold is an add; the sign of the direction-1 tap is applied once per p1.
+// Tap index p = 3 * cluster + sub.  The two inner levels keep positive and
+// negative parts apart so that every fold is an add; the sign of the
+// direction-1 tap is applied once per p1.
 template <bool CONTIG>
 __device__ __forceinline__ void contract3(const char *__restrict__ Gb, uint32_t b, const int32_t cT[4],
                                           const int32_t cB[4], const int32_t st[4], int64_t acc[27]) {
@@ -438,11 +480,14 @@ __device__ __forceinline__ double contract_fp(const int64_t acc[27], const doubl
 // operator a0 are live:
 //   aa: -2 M1, + T0, + B2;   bb: -2 M1, + T2, + B0;   ab: -(M0 + M2), + T1, + B1
 // (M1 is visited twice, 10 steps in all).  WAVES bounds the registers so that
-// that many wavefronts fit on a SIMD.
-template <bool CONTIG, int WAVES, int WX>
-__global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs a) {
-    int64_t x, y;
-    if (!pixel_of_thread_wx<WX>(a.H, a.W, x, y)) return;
+// that many wavefronts fit on a SIMD; WX is the wavefront's pixel width.
+template <bool CONTIG, int WAVES, int WX, bool BATCH>
+__global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, const GatherArgs *__restrict__ table,
+                                                            const int64_t *__restrict__ prefix, int B) {
+    GatherArgs a;
+    int64_t bx, by, x, y;
+    if (!tile_of_block<BATCH>(one, table, prefix, B, WX, 256 / WX, a, bx, by)) return;
+    if (!pixel_wx<WX>(a, bx, by, x, y)) return;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const char *Gb = static_cast<const char *>(a.G);
     const uint32_t base = (uint32_t)(((y + a.pad_top) * a.Wp + (x + a.pad_left)) * 8);
@@ -514,9 +559,20 @@ __global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs a) {
 
 // Plain FP64 counterpart: FP64 running sums and FP64 tap weights
 //   T0:(1-p)^2 T1:2p(1-p) T2:p^2 M0:-2p(1-p) M1:-2((1-p)^2+p^2) M2:-2p(1-p) B0:p^2 B1:2p(1-p) B2:(1-p)^2
-__global__ __launch_bounds__(256) void k_gather_t2n4_fp64(GatherArgs a) {
-    int64_t x, y;
-    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+__device__ __forceinline__ void offsets9(int32_t R, int32_t off, int32_t o[9]) {
+    const int32_t t = 2 * R * off, m = -2 * off, b = (-2 * R - 4) * off;
+    o[0] = t; o[1] = t + off; o[2] = t + 2 * off;
+    o[3] = m; o[4] = m + off; o[5] = m + 2 * off;
+    o[6] = b; o[7] = b + off; o[8] = b + 2 * off;
+}
+
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_gather_t2n4_fp64(GatherArgs one, const GatherArgs *__restrict__ table,
+                                                          const int64_t *__restrict__ prefix, int B) {
+    GatherArgs a;
+    int64_t bx, by, x, y;
+    if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
+    if (!pixel_16x16(a, bx, by, x, y)) return;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const double *G = static_cast<const double *>(a.G);
     const int32_t base = (int32_t)((y + a.pad_top) * a.Wp + (x + a.pad_left));
@@ -556,67 +612,131 @@ __global__ __launch_bounds__(256) void k_gather_t2n4_fp64(GatherArgs a) {
     if (a.out) a.out[idx] = (float)(tot / den);
 }
 
-// Kernel variant of the tied order-2 four-direction contraction; the tuner
-// (BSF_T2N4_VARIANT) may override the default.
-int t2n4_variant() {
-    static int v = [] {
-        const char *e = getenv("BSF_T2N4_VARIANT");
-        return e ? atoi(e) : 0;
-    }();
-    return v;
+// Pixel-tile shape of the kernel run_gather picks for a plan.
+struct GatherShape {
+    int kind;  // 0 int, 1 generic real, 2 tied order-2 exact, 3 tied order-2 fp64
+    int tile_w, tile_h;
+};
+
+GatherShape gather_shape(const Plan &p, const GatherArgs &a) {
+    GatherShape s{1, kTile, kTile};
+    if (p.mode == BSF_STEPS_INT) {
+        s.kind = 0;
+    } else if (p.n_dirs == 4 && p.order == 2 && p.tied && p.Hp * p.Wp * 8 < (int64_t(1) << 32)) {
+        if (p.arith == BSF_ARITH_FP64) {
+            s.kind = 3;
+        } else {
+            s.kind = 2;
+            const bool contig = a.off[6] == 1;
+            const int wx = contig ? tuning().gather_wx : 16;
+            s.tile_w = wx;
+            s.tile_h = 256 / wx;
+        }
+    }
+    return s;
+}
+
+template <bool BATCH>
+bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs *table, const int64_t *prefix, int B,
+                         int64_t total_tiles, hipStream_t st) {
+    const GatherShape s = gather_shape(p, one);
+    dim3 grid;
+    if (BATCH) {
+        grid = dim3((unsigned)total_tiles);
+    } else {
+        grid = dim3((unsigned)((p.W + s.tile_w - 1) / s.tile_w), (unsigned)((p.H + s.tile_h - 1) / s.tile_h));
+    }
+    dim3 block(256);
+    const bool fp64 = p.arith == BSF_ARITH_FP64;
+    if (s.kind == 0) {
+        if (p.M == 4) {
+            if (fp64) hipLaunchKernelGGL((k_gather_int<double, 4, BATCH>), grid, block, 0, st, one, table, prefix, B);
+            else hipLaunchKernelGGL((k_gather_int<int64_t, 4, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        } else {
+            if (fp64) hipLaunchKernelGGL((k_gather_int<double, 0, BATCH>), grid, block, 0, st, one, table, prefix, B);
+            else hipLaunchKernelGGL((k_gather_int<int64_t, 0, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        }
+    } else if (s.kind == 3) {
+        hipLaunchKernelGGL((k_gather_t2n4_fp64<BATCH>), grid, block, 0, st, one, table, prefix, B);
+    } else if (s.kind == 2) {
+        const bool contig = one.off[6] == 1;
+        if (!contig) hipLaunchKernelGGL((k_gather_t2n4<false, 2, 16, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        else if (s.tile_w == 8) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 8, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        else if (s.tile_w == 32) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 32, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        else if (s.tile_w == 64) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 64, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        else hipLaunchKernelGGL((k_gather_t2n4<true, 2, 16, BATCH>), grid, block, 0, st, one, table, prefix, B);
+    } else {
+        if (fp64) hipLaunchKernelGGL((k_gather_real_generic<double, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        else hipLaunchKernelGGL((k_gather_real_generic<int64_t, BATCH>), grid, block, 0, st, one, table, prefix, B);
+    }
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
 }
 
 }  // namespace
 
 bsf_status run_bound(const Plan &p, const Src &src, const float *steps, int32_t F_request, int32_t *status,
                      hipStream_t st, bool recheck) {
-    hipLaunchKernelGGL(k_status_begin, dim3(1), dim3(64), 0, st, status, F_request, recheck ? 1 : 0);
+    BoundJob job{steps, (!recheck && src.kind == SRC_F32) ? static_cast<const float *>(src.img) : nullptr,
+                 p.H, p.W, src.pitch, status};
+    hipLaunchKernelGGL((k_status_begin<false>), dim3(1), dim3(64), 0, st, job, nullptr, F_request, recheck ? 1 : 0);
     BSF_HIP_CHECK(hipGetLastError());
     int64_t blocks = p.H < 2048 ? p.H : 2048;
     if (blocks < 1) blocks = 1;
-    const float *img = (!recheck && src.kind == SRC_F32) ? static_cast<const float *>(src.img) : nullptr;
-    hipLaunchKernelGGL(k_bound, dim3((unsigned)blocks), dim3(256), 0, st, steps, p.H, p.W, p.planes,
-                       p.tied ? p.order : 1, p.mode, p.max_step, img, src.pitch, status);
+    hipLaunchKernelGGL((k_bound<false>), dim3((unsigned)blocks), dim3(256), 0, st, job, nullptr, nullptr, 1, p.planes,
+                       p.tied ? p.order : 1, p.mode, p.max_step);
     BSF_HIP_CHECK(hipGetLastError());
     if (recheck)
         hipLaunchKernelGGL(k_check_F, dim3(1), dim3(64), 0, st, status);
     else
-        hipLaunchKernelGGL(k_choose_F, dim3(1), dim3(64), 0, st, status, src.kind, p.arith);
+        hipLaunchKernelGGL((k_choose_F<false>), dim3(1), dim3(64), 0, st, job, nullptr, src.kind, p.arith);
     BSF_HIP_CHECK(hipGetLastError());
     return BSF_OK;
 }
 
 bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st) {
     if (p.H == 0 || p.W == 0) return BSF_OK;
-    dim3 grid((unsigned)((p.W + kTile - 1) / kTile), (unsigned)((p.H + kTile - 1) / kTile));
-    dim3 block(256);
-    const bool fp64 = p.arith == BSF_ARITH_FP64;
-    if (p.mode == BSF_STEPS_INT) {
-        if (p.M == 4) {
-            if (fp64) hipLaunchKernelGGL((k_gather_int<double, 4>), grid, block, 0, st, a);
-            else hipLaunchKernelGGL((k_gather_int<int64_t, 4>), grid, block, 0, st, a);
-        } else {
-            if (fp64) hipLaunchKernelGGL((k_gather_int<double, 0>), grid, block, 0, st, a);
-            else hipLaunchKernelGGL((k_gather_int<int64_t, 0>), grid, block, 0, st, a);
-        }
-    } else if (p.n_dirs == 4 && p.order == 2 && p.tied && p.Hp * p.Wp * 8 < (int64_t(1) << 32)) {
-        const int v = t2n4_variant();
-        const bool contig = a.off[6] == 1;
-        // wavefront width in pixels (the tuner's choice)
-        const int wx = v == 1 ? 8 : v == 3 ? 32 : v == 4 ? 64 : 16;
-        dim3 g2((unsigned)((p.W + wx - 1) / wx), (unsigned)((p.H + 256 / wx - 1) / (256 / wx)));
-        if (fp64) hipLaunchKernelGGL(k_gather_t2n4_fp64, grid, block, 0, st, a);
-        else if (!contig) hipLaunchKernelGGL((k_gather_t2n4<false, 2, 16>), g2, block, 0, st, a);
-        else if (wx == 8) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 8>), g2, block, 0, st, a);
-        else if (wx == 32) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 32>), g2, block, 0, st, a);
-        else if (wx == 64) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 64>), g2, block, 0, st, a);
-        else hipLaunchKernelGGL((k_gather_t2n4<true, 2, 16>), g2, block, 0, st, a);
-    } else {
-        if (fp64) hipLaunchKernelGGL((k_gather_real_generic<double>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_gather_real_generic<int64_t>), grid, block, 0, st, a);
+    return launch_gather<false>(p, a, nullptr, nullptr, 1, 0, st);
+}
+
+int gather_variant(const Plan &p, const GatherArgs &a) {
+    const GatherShape s = gather_shape(p, a);
+    return s.kind | (s.tile_w << 4) | ((a.off[6] == 1) << 12) | ((p.M == 4) << 13) | (p.arith << 14);
+}
+
+int64_t gather_tiles(const Plan &p, const GatherArgs &a) {
+    const GatherShape s = gather_shape(p, a);
+    return ((p.W + s.tile_w - 1) / s.tile_w) * ((p.H + s.tile_h - 1) / s.tile_h);
+}
+
+bsf_status run_gather_batch(const Plan &p0, const GatherArgs &a0, const GatherArgs *table, const int64_t *prefix,
+                            int B, int64_t total_tiles, hipStream_t st) {
+    if (total_tiles <= 0) return BSF_OK;
+    return launch_gather<true>(p0, a0, table, prefix, B, total_tiles, st);
+}
+
+bsf_status run_bound_batch(const Plan &p0, int img_kind, int32_t F_request, const void *jobs, const int64_t *prefix,
+                           int B, int64_t total_rows, hipStream_t st) {
+    const BoundJob *bj = static_cast<const BoundJob *>(jobs);
+    BoundJob none{};
+    hipLaunchKernelGGL((k_status_begin<true>), dim3((unsigned)B), dim3(64), 0, st, none, bj, F_request, 0);
+    BSF_HIP_CHECK(hipGetLastError());
+    if (total_rows > 0) {
+        hipLaunchKernelGGL((k_bound<true>), dim3((unsigned)total_rows), dim3(256), 0, st, none, bj, prefix, B,
+                           p0.planes, p0.tied ? p0.order : 1, p0.mode, p0.max_step);
+        BSF_HIP_CHECK(hipGetLastError());
     }
+    hipLaunchKernelGGL((k_choose_F<true>), dim3((unsigned)B), dim3(64), 0, st, none, bj, img_kind, p0.arith);
     BSF_HIP_CHECK(hipGetLastError());
     return BSF_OK;
+}
+
+size_t bound_job_bytes() { return sizeof(BoundJob); }
+
+void make_bound_job(const float *steps, const float *img, int64_t H, int64_t W, int64_t pitch, int32_t *status,
+                    void *out) {
+    BoundJob j{steps, img, H, W, pitch, status};
+    memcpy(out, &j, sizeof(j));
 }
 
 }  // namespace bsf

@@ -10,6 +10,9 @@
 // elements of one row.  A tile's carry comes from the tile before it on the
 // same lines, so the scan runs in three phases (tile aggregates, a per-line scan
 // of aggregates, the final rescan), none of which waits on another workgroup.
+//
+// Every kernel runs either on one image (arguments by value) or on a batch
+// (BATCH: a work list over images, each block looking up its image's job).
 #include <type_traits>
 
 #include "bsf_common.h"
@@ -19,7 +22,6 @@ namespace {
 
 constexpr int kRowThreads = 256;
 constexpr int kRowChunk = kRowThreads * 4;
-constexpr int kLineTL = 64;  // steps per line tile
 
 template <typename V>
 __device__ __forceinline__ V shfl_up64(V v, int d) {
@@ -70,12 +72,36 @@ __device__ __forceinline__ V load_src(const V *G, int64_t Wp, const Src &src, in
     }
 }
 
-template <typename V, int ORDER, int SRC>
-__global__ __launch_bounds__(kRowThreads) void k_row_scan(V *__restrict__ G, int64_t Wp, int dir, Src src,
-                                                          const int32_t *__restrict__ status) {
+// The job of this block and its local work item: a by-value job, or the
+// batch's job table searched with the block index.
+template <bool BATCH>
+__device__ __forceinline__ bool job_of_block(const ScanJob &one, const ScanJob *__restrict__ jobs,
+                                             const int64_t *__restrict__ prefix, int B, ScanJob &job,
+                                             int64_t &item) {
+    if constexpr (BATCH) {
+        const int64_t gi = blockIdx.x;
+        const int b = find_job(prefix, B, gi);
+        job = jobs[b];
+        item = gi - prefix[b];
+        return item < prefix[b + 1] - prefix[b];
+    } else {
+        job = one;
+        item = blockIdx.x;
+        return true;
+    }
+}
+
+template <typename V, int ORDER, int SRC, bool BATCH>
+__global__ __launch_bounds__(kRowThreads) void k_row_scan(ScanJob one, const ScanJob *__restrict__ jobs,
+                                                          const int64_t *__restrict__ prefix, int B) {
     __shared__ V lds[4];
-    const int64_t row = blockIdx.x;
-    const int F = (SRC == SRC_F32) ? status[ST_F_USED] : 0;
+    ScanJob job;
+    int64_t row;
+    if (!job_of_block<BATCH>(one, jobs, prefix, B, job, row)) return;
+    V *__restrict__ G = static_cast<V *>(job.G);
+    const int64_t Wp = job.Wp;
+    const int dir = job.dir;
+    const int F = (SRC == SRC_F32) ? job.status[ST_F_USED] : 0;
     V carry[ORDER];
 #pragma unroll
     for (int o = 0; o < ORDER; ++o) carry[o] = V(0);
@@ -85,7 +111,7 @@ __global__ __launch_bounds__(kRowThreads) void k_row_scan(V *__restrict__ G, int
         for (int i = 0; i < 4; ++i) {
             const int64_t e = c0 + 4 * threadIdx.x + i;
             const int64_t col = dir > 0 ? e : Wp - 1 - e;
-            v[i] = (e < Wp) ? load_src<V, SRC>(G, Wp, src, F, row, col) : V(0);
+            v[i] = (e < Wp) ? load_src<V, SRC>(G, Wp, job.src, F, row, col) : V(0);
         }
 #pragma unroll
         for (int o = 0; o < ORDER; ++o) {
@@ -111,15 +137,6 @@ __global__ __launch_bounds__(kRowThreads) void k_row_scan(V *__restrict__ G, int
 // ----------------------------------------------------------------------------
 // Sheared line tiles for dy != 0.
 // ----------------------------------------------------------------------------
-struct LineGeom {
-    int dx, dy, ay;
-    int64_t Hp, Wp;
-    int64_t T;         // steps per residue class (rows / |dy|, rounded up)
-    int64_t c_lo;      // start column of the first line
-    int64_t n_groups;  // groups of 64 lines
-    int64_t n_chunks;  // chunks of kLineTL steps
-};
-
 __device__ __forceinline__ void line_cell(const LineGeom &g, int64_t q, int64_t c0, int64_t t, int64_t &row,
                                           int64_t &col, bool &inside) {
     row = g.dy > 0 ? q + t * g.ay : g.Hp - 1 - q - t * g.ay;
@@ -136,15 +153,20 @@ __device__ __forceinline__ V binom_small(int64_t n, int m) {
     return V((n * (n - 1) * (n - 2)) / 6);
 }
 
-template <typename V, int ORDER, int SRC>
-__global__ __launch_bounds__(64) void k_line_aggregate(const V *__restrict__ G, LineGeom g, Src src,
-                                                       const int32_t *__restrict__ status, V *__restrict__ aux) {
+template <typename V, int ORDER, int SRC, bool BATCH>
+__global__ __launch_bounds__(64) void k_line_aggregate(ScanJob one, const ScanJob *__restrict__ jobs,
+                                                       const int64_t *__restrict__ prefix, int B) {
+    ScanJob job;
+    int64_t idx;
+    if (!job_of_block<BATCH>(one, jobs, prefix, B, job, idx)) return;
+    const LineGeom &g = job.g;
+    const V *__restrict__ G = static_cast<const V *>(job.G);
+    V *__restrict__ aux = static_cast<V *>(job.aux);
     const int lane = threadIdx.x;
-    const int64_t idx = blockIdx.x;
     const int64_t gi = idx % g.n_groups, ch = (idx / g.n_groups) % g.n_chunks, q = idx / (g.n_groups * g.n_chunks);
     const int64_t c0 = g.c_lo + gi * 64 + lane;
-    const int64_t t0 = ch * kLineTL, t1 = min(g.T, t0 + kLineTL);
-    const int F = (SRC == SRC_F32) ? status[ST_F_USED] : 0;
+    const int64_t t0 = ch * g.tl, t1 = min(g.T, t0 + g.tl);
+    const int F = (SRC == SRC_F32) ? job.status[ST_F_USED] : 0;
     V s[ORDER];
 #pragma unroll
     for (int o = 0; o < ORDER; ++o) s[o] = V(0);
@@ -152,7 +174,7 @@ __global__ __launch_bounds__(64) void k_line_aggregate(const V *__restrict__ G, 
         int64_t row, col;
         bool in;
         line_cell(g, q, c0, t, row, col, in);
-        const V v = in ? load_src<V, SRC>(G, g.Wp, src, F, row, col) : V(0);
+        const V v = in ? load_src<V, SRC>(G, g.Wp, job.src, F, row, col) : V(0);
         s[0] += v;
 #pragma unroll
         for (int o = 1; o < ORDER; ++o) s[o] += s[o - 1];
@@ -161,16 +183,22 @@ __global__ __launch_bounds__(64) void k_line_aggregate(const V *__restrict__ G, 
     for (int o = 0; o < ORDER; ++o) aux[(idx * ORDER + o) * 64 + lane] = s[o];
 }
 
-template <typename V, int ORDER>
-__global__ __launch_bounds__(64) void k_line_carry(LineGeom g, V *__restrict__ aux) {
+template <typename V, int ORDER, bool BATCH>
+__global__ __launch_bounds__(64) void k_line_carry(ScanJob one, const ScanJob *__restrict__ jobs,
+                                                   const int64_t *__restrict__ prefix, int B) {
+    ScanJob job;
+    int64_t grp;
+    if (!job_of_block<BATCH>(one, jobs, prefix, B, job, grp)) return;
+    const LineGeom &g = job.g;
+    V *__restrict__ aux = static_cast<V *>(job.aux);
     const int lane = threadIdx.x;
-    const int64_t gi = blockIdx.x % g.n_groups, q = blockIdx.x / g.n_groups;
+    const int64_t gi = grp % g.n_groups, q = grp / g.n_groups;
     V state[ORDER];
 #pragma unroll
     for (int o = 0; o < ORDER; ++o) state[o] = V(0);
     for (int64_t ch = 0; ch < g.n_chunks; ++ch) {
         const int64_t idx = (q * g.n_chunks + ch) * g.n_groups + gi;
-        const int64_t L = min(g.T, (ch + 1) * kLineTL) - ch * kLineTL;
+        const int64_t L = min(g.T, (ch + 1) * g.tl) - ch * g.tl;
         V agg[ORDER];
 #pragma unroll
         for (int o = 0; o < ORDER; ++o) {
@@ -191,15 +219,20 @@ __global__ __launch_bounds__(64) void k_line_carry(LineGeom g, V *__restrict__ a
     }
 }
 
-template <typename V, int ORDER, int SRC>
-__global__ __launch_bounds__(64) void k_line_final(V *__restrict__ G, LineGeom g, Src src,
-                                                   const int32_t *__restrict__ status, const V *__restrict__ aux) {
+template <typename V, int ORDER, int SRC, bool BATCH>
+__global__ __launch_bounds__(64) void k_line_final(ScanJob one, const ScanJob *__restrict__ jobs,
+                                                   const int64_t *__restrict__ prefix, int B) {
+    ScanJob job;
+    int64_t idx;
+    if (!job_of_block<BATCH>(one, jobs, prefix, B, job, idx)) return;
+    const LineGeom &g = job.g;
+    V *__restrict__ G = static_cast<V *>(job.G);
+    const V *__restrict__ aux = static_cast<const V *>(job.aux);
     const int lane = threadIdx.x;
-    const int64_t idx = blockIdx.x;
     const int64_t gi = idx % g.n_groups, ch = (idx / g.n_groups) % g.n_chunks, q = idx / (g.n_groups * g.n_chunks);
     const int64_t c0 = g.c_lo + gi * 64 + lane;
-    const int64_t t0 = ch * kLineTL, t1 = min(g.T, t0 + kLineTL);
-    const int F = (SRC == SRC_F32) ? status[ST_F_USED] : 0;
+    const int64_t t0 = ch * g.tl, t1 = min(g.T, t0 + g.tl);
+    const int F = (SRC == SRC_F32) ? job.status[ST_F_USED] : 0;
     V s[ORDER];
 #pragma unroll
     for (int o = 0; o < ORDER; ++o) s[o] = aux[(idx * ORDER + o) * 64 + lane];
@@ -207,7 +240,7 @@ __global__ __launch_bounds__(64) void k_line_final(V *__restrict__ G, LineGeom g
         int64_t row, col;
         bool in;
         line_cell(g, q, c0, t, row, col, in);
-        const V v = in ? load_src<V, SRC>(G, g.Wp, src, F, row, col) : V(0);
+        const V v = in ? load_src<V, SRC>(G, g.Wp, job.src, F, row, col) : V(0);
         s[0] += v;
 #pragma unroll
         for (int o = 1; o < ORDER; ++o) s[o] += s[o - 1];
@@ -215,11 +248,103 @@ __global__ __launch_bounds__(64) void k_line_final(V *__restrict__ G, LineGeom g
     }
 }
 
-LineGeom line_geom(int dx, int dy, int64_t Hp, int64_t Wp) {
+// Launch one pass: a by-value job (jobs == nullptr) or a batch.
+template <typename V, int ORDER, int SRC>
+bsf_status pass_one(int dy, const ScanJob &one, const ScanJob *jobs, const int64_t *prefix_items,
+                    int64_t total_items, const int64_t *prefix_groups, int64_t total_groups, int B,
+                    hipStream_t st) {
+    const bool batch = jobs != nullptr;
+    if (total_items <= 0) return BSF_OK;
+    if (dy == 0) {
+        if (batch)
+            hipLaunchKernelGGL((k_row_scan<V, ORDER, SRC, true>), dim3((unsigned)total_items), dim3(kRowThreads), 0,
+                               st, one, jobs, prefix_items, B);
+        else
+            hipLaunchKernelGGL((k_row_scan<V, ORDER, SRC, false>), dim3((unsigned)total_items), dim3(kRowThreads),
+                               0, st, one, jobs, prefix_items, B);
+        BSF_HIP_CHECK(hipGetLastError());
+        return BSF_OK;
+    }
+    if (batch) {
+        hipLaunchKernelGGL((k_line_aggregate<V, ORDER, SRC, true>), dim3((unsigned)total_items), dim3(64), 0, st,
+                           one, jobs, prefix_items, B);
+        hipLaunchKernelGGL((k_line_carry<V, ORDER, true>), dim3((unsigned)total_groups), dim3(64), 0, st, one, jobs,
+                           prefix_groups, B);
+        hipLaunchKernelGGL((k_line_final<V, ORDER, SRC, true>), dim3((unsigned)total_items), dim3(64), 0, st, one,
+                           jobs, prefix_items, B);
+    } else {
+        hipLaunchKernelGGL((k_line_aggregate<V, ORDER, SRC, false>), dim3((unsigned)total_items), dim3(64), 0, st,
+                           one, jobs, prefix_items, B);
+        hipLaunchKernelGGL((k_line_carry<V, ORDER, false>), dim3((unsigned)total_groups), dim3(64), 0, st, one,
+                           jobs, prefix_groups, B);
+        hipLaunchKernelGGL((k_line_final<V, ORDER, SRC, false>), dim3((unsigned)total_items), dim3(64), 0, st, one,
+                           jobs, prefix_items, B);
+    }
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
+}
+
+template <typename V, int ORDER>
+bsf_status pass_dispatch_src(int src_kind, int dy, const ScanJob &one, const ScanJob *jobs, const int64_t *pi,
+                             int64_t ti, const int64_t *pg, int64_t tg, int B, hipStream_t st) {
+    switch (src_kind) {
+    case SRC_WINDOW: return pass_one<V, ORDER, SRC_WINDOW>(dy, one, jobs, pi, ti, pg, tg, B, st);
+    case SRC_F32: return pass_one<V, ORDER, SRC_F32>(dy, one, jobs, pi, ti, pg, tg, B, st);
+    case SRC_U8: return pass_one<V, ORDER, SRC_U8>(dy, one, jobs, pi, ti, pg, tg, B, st);
+    case SRC_U16: return pass_one<V, ORDER, SRC_U16>(dy, one, jobs, pi, ti, pg, tg, B, st);
+    }
+    return BSF_E_INVALID;
+}
+
+template <typename V>
+bsf_status pass_dispatch(int order, int src_kind, int dy, const ScanJob &one, const ScanJob *jobs, const int64_t *pi,
+                         int64_t ti, const int64_t *pg, int64_t tg, int B, hipStream_t st) {
+    switch (order) {
+    case 1: return pass_dispatch_src<V, 1>(src_kind, dy, one, jobs, pi, ti, pg, tg, B, st);
+    case 2: return pass_dispatch_src<V, 2>(src_kind, dy, one, jobs, pi, ti, pg, tg, B, st);
+    case 3: return pass_dispatch_src<V, 3>(src_kind, dy, one, jobs, pi, ti, pg, tg, B, st);
+    case 4: return pass_dispatch_src<V, 4>(src_kind, dy, one, jobs, pi, ti, pg, tg, B, st);
+    }
+    return BSF_E_UNSUPPORTED;
+}
+
+size_t line_aux_bytes(int dx, int dy, int64_t Hp, int64_t Wp, int order) {
+    LineGeom g = line_geom(dx, dy, Hp, Wp, tuning().line_tl);
+    return (size_t)g.ay * g.n_chunks * g.n_groups * 64 * order * 8;
+}
+
+// One pass of one image through the single-image kernels.
+bsf_status pass_single(int arith, int order, int dx, int dy, int64_t Hp, int64_t Wp, const Src &src, void *G,
+                       void *aux, const int32_t *status, hipStream_t st) {
+    ScanJob job{};
+    job.G = G;
+    job.aux = aux;
+    job.status = status;
+    job.src = src;
+    job.Hp = Hp;
+    job.Wp = Wp;
+    job.dir = dx > 0 ? 1 : -1;
+    int64_t items, groups = 0;
+    if (dy == 0) {
+        items = Hp;
+    } else {
+        job.g = line_geom(dx, dy, Hp, Wp, tuning().line_tl);
+        items = job.g.ay * job.g.n_chunks * job.g.n_groups;
+        groups = job.g.ay * job.g.n_groups;
+    }
+    if (arith == BSF_ARITH_FP64)
+        return pass_dispatch<double>(order, src.kind, dy, job, nullptr, nullptr, items, nullptr, groups, 1, st);
+    return pass_dispatch<int64_t>(order, src.kind, dy, job, nullptr, nullptr, items, nullptr, groups, 1, st);
+}
+
+}  // namespace
+
+LineGeom line_geom(int dx, int dy, int64_t Hp, int64_t Wp, int tl) {
     LineGeom g;
     g.dx = dx;
     g.dy = dy;
     g.ay = dy > 0 ? dy : -dy;
+    g.tl = tl;
     g.Hp = Hp;
     g.Wp = Wp;
     g.T = (Hp + g.ay - 1) / g.ay;
@@ -227,69 +352,19 @@ LineGeom line_geom(int dx, int dy, int64_t Hp, int64_t Wp) {
     g.c_lo = span > 0 ? -span : 0;
     const int64_t c_hi = span < 0 ? Wp - span : Wp;
     g.n_groups = (c_hi - g.c_lo + 63) / 64;
-    g.n_chunks = (g.T + kLineTL - 1) / kLineTL;
+    g.n_chunks = (g.T + tl - 1) / tl;
     return g;
 }
-
-size_t line_aux_bytes(int dx, int dy, int64_t Hp, int64_t Wp, int order) {
-    LineGeom g = line_geom(dx, dy, Hp, Wp);
-    return (size_t)g.ay * g.n_chunks * g.n_groups * 64 * order * 8;
-}
-
-template <typename V, int ORDER, int SRC>
-bsf_status pass_one(int dx, int dy, int64_t Hp, int64_t Wp, const Src &src, V *G, V *aux, const int32_t *status,
-                    hipStream_t st) {
-    if (dy == 0) {
-        hipLaunchKernelGGL((k_row_scan<V, ORDER, SRC>), dim3((unsigned)Hp), dim3(kRowThreads), 0, st, G, Wp,
-                           dx > 0 ? 1 : -1, src, status);
-        BSF_HIP_CHECK(hipGetLastError());
-        return BSF_OK;
-    }
-    LineGeom g = line_geom(dx, dy, Hp, Wp);
-    const int64_t tiles = g.ay * g.n_chunks * g.n_groups;
-    hipLaunchKernelGGL((k_line_aggregate<V, ORDER, SRC>), dim3((unsigned)tiles), dim3(64), 0, st, G, g, src, status,
-                       aux);
-    BSF_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((k_line_carry<V, ORDER>), dim3((unsigned)(g.ay * g.n_groups)), dim3(64), 0, st, g, aux);
-    BSF_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((k_line_final<V, ORDER, SRC>), dim3((unsigned)tiles), dim3(64), 0, st, G, g, src, status,
-                       aux);
-    BSF_HIP_CHECK(hipGetLastError());
-    return BSF_OK;
-}
-
-template <typename V, int ORDER>
-bsf_status pass_dispatch_src(int dx, int dy, int64_t Hp, int64_t Wp, const Src &src, V *G, V *aux,
-                             const int32_t *status, hipStream_t st) {
-    switch (src.kind) {
-    case SRC_WINDOW: return pass_one<V, ORDER, SRC_WINDOW>(dx, dy, Hp, Wp, src, G, aux, status, st);
-    case SRC_F32: return pass_one<V, ORDER, SRC_F32>(dx, dy, Hp, Wp, src, G, aux, status, st);
-    case SRC_U8: return pass_one<V, ORDER, SRC_U8>(dx, dy, Hp, Wp, src, G, aux, status, st);
-    case SRC_U16: return pass_one<V, ORDER, SRC_U16>(dx, dy, Hp, Wp, src, G, aux, status, st);
-    }
-    return BSF_E_INVALID;
-}
-
-template <typename V>
-bsf_status pass_dispatch(int order, int dx, int dy, int64_t Hp, int64_t Wp, const Src &src, V *G, V *aux,
-                         const int32_t *status, hipStream_t st) {
-    switch (order) {
-    case 1: return pass_dispatch_src<V, 1>(dx, dy, Hp, Wp, src, G, aux, status, st);
-    case 2: return pass_dispatch_src<V, 2>(dx, dy, Hp, Wp, src, G, aux, status, st);
-    case 3: return pass_dispatch_src<V, 3>(dx, dy, Hp, Wp, src, G, aux, status, st);
-    case 4: return pass_dispatch_src<V, 4>(dx, dy, Hp, Wp, src, G, aux, status, st);
-    }
-    return BSF_E_UNSUPPORTED;
-}
-
-}  // namespace
 
 size_t scan_aux_bytes(const Plan &p) {
     size_t m = 0;
     for (int k = 0; k < p.n_dirs; ++k) {
+        // both the forward pass (dx, dy) and the transposed one (-dx, -dy)
         if (p.dy[k] == 0) continue;
         size_t b = line_aux_bytes(p.dx[k], p.dy[k], p.Hp, p.Wp, p.order);
+        size_t bt = line_aux_bytes(-p.dx[k], -p.dy[k], p.Hp, p.Wp, p.order);
         if (b > m) m = b;
+        if (bt > m) m = bt;
     }
     return align_up(m);
 }
@@ -298,13 +373,7 @@ bsf_status run_preintegrate(const Plan &p, const Src &src, void *G, void *aux, c
                             hipStream_t st) {
     Src s = src;
     for (int k = 0; k < p.n_dirs; ++k) {
-        bsf_status r;
-        if (p.arith == BSF_ARITH_FP64)
-            r = pass_dispatch<double>(p.order, p.dx[k], p.dy[k], p.Hp, p.Wp, s, (double *)G, (double *)aux, status,
-                                      st);
-        else
-            r = pass_dispatch<int64_t>(p.order, p.dx[k], p.dy[k], p.Hp, p.Wp, s, (int64_t *)G, (int64_t *)aux,
-                                       status, st);
+        bsf_status r = pass_single(p.arith, p.order, p.dx[k], p.dy[k], p.Hp, p.Wp, s, G, aux, status, st);
         if (r != BSF_OK) return r;
         s.kind = SRC_WINDOW;
     }
@@ -315,11 +384,23 @@ bsf_status run_preintegrate_transpose(const Plan &p, void *G, void *aux, hipStre
     Src s{};
     s.kind = SRC_WINDOW;
     for (int k = p.n_dirs - 1; k >= 0; --k) {
-        bsf_status r = pass_dispatch<int64_t>(p.order, -p.dx[k], -p.dy[k], p.Hp, p.Wp, s, (int64_t *)G,
-                                              (int64_t *)aux, nullptr, st);
+        bsf_status r =
+            pass_single(BSF_ARITH_EXACT, p.order, -p.dx[k], -p.dy[k], p.Hp, p.Wp, s, G, aux, nullptr, st);
         if (r != BSF_OK) return r;
     }
     return BSF_OK;
+}
+
+bsf_status run_pass_batch(int arith, int order, int src_kind, int dx, int dy, const ScanJob *jobs,
+                          const int64_t *prefix_items, int64_t total_items, const int64_t *prefix_groups,
+                          int64_t total_groups, int B, hipStream_t st) {
+    (void)dx;
+    ScanJob none{};
+    if (arith == BSF_ARITH_FP64)
+        return pass_dispatch<double>(order, src_kind, dy, none, jobs, prefix_items, total_items, prefix_groups,
+                                     total_groups, B, st);
+    return pass_dispatch<int64_t>(order, src_kind, dy, none, jobs, prefix_items, total_items, prefix_groups,
+                                  total_groups, B, st);
 }
 
 }  // namespace bsf

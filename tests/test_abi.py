@@ -138,3 +138,78 @@ def test_entry_points_validate_before_launch():
     r = L.bsf_filter_backward(ctypes.byref(cfg), 8, 8, ctypes.c_void_p(16), ctypes.c_void_p(16), NULL,
                               ctypes.c_void_p(16), NULL, ctypes.c_void_p(16), 64, NULL)
     assert r == bsf.E_WORKSPACE
+
+
+def test_tuning_setter_validates_and_round_trips():
+    L = bsf.lib()
+    wx0, tl0 = bsf.get_tuning()
+    assert (wx0, tl0) == (16, 64)
+    try:
+        for wx, tl in ((8, 16), (32, 256), (64, 4096)):
+            bsf.set_tuning(wx, tl)
+            assert bsf.get_tuning() == (wx, tl)
+        for wx, tl in ((12, 64), (0, 64), (16, 8), (16, 96), (16, 8192)):
+            assert L.bsf_set_tuning(wx, tl) == bsf.E_INVALID
+            assert bsf.get_tuning() == (64, 4096)          # unchanged
+        # the carries of the sheared scans scale with the tile count
+        cfg = bsf.Config(order=2, max_step=9.0)
+        bsf.set_tuning(16, 16)
+        small_tiles = geo(cfg, 512, 512).workspace_bytes
+        bsf.set_tuning(16, 512)
+        big_tiles = geo(cfg, 512, 512).workspace_bytes
+        assert small_tiles > big_tiles
+    finally:
+        bsf.set_tuning(wx0, tl0)
+
+
+def _descs(shapes, fake=0x1000):
+    arr = (bsf._ImageDesc * max(len(shapes), 1))()
+    for b, (H, W) in enumerate(shapes):
+        d = arr[b]
+        d.img = d.steps = d.out = fake if H * W else 0
+        d.H, d.W, d.pitch = H, W, W
+    return arr
+
+
+def test_batched_workspace_is_the_sum_of_image_workspaces():
+    L = bsf.lib()
+    cfg = bsf.Config(order=2, max_step=9.0)
+    c = cfg.c()
+    shapes = [(40, 52), (0, 7), (128, 96), (17, 1)]
+    total = L.bsf_batched_workspace_bytes(ctypes.byref(c), len(shapes), _descs(shapes))
+    per_image = sum((geo(cfg, H, W).workspace_bytes + 255) // 256 * 256 for H, W in shapes)
+    # batch status block + launch tables + one single-image workspace per image
+    assert total > per_image + 256
+    assert total - per_image - 256 < 64 * 1024
+    one = L.bsf_batched_workspace_bytes(ctypes.byref(c), 1, _descs(shapes[:1]))
+    assert one < total
+    assert L.bsf_batched_workspace_bytes(ctypes.byref(c), 0, None) > 0
+
+
+def test_batched_entry_point_validates_before_launch():
+    L = bsf.lib()
+    cfg = bsf.Config(order=2, max_step=9.0)
+    c = cfg.c()
+    shapes = [(40, 52), (30, 31)]
+    d = _descs(shapes)
+    need = L.bsf_batched_workspace_bytes(ctypes.byref(c), 2, d)
+    ws = ctypes.c_void_p(0x100000)
+    # invalid count, missing descriptors, missing workspace
+    assert L.bsf_batched_workspace_bytes(ctypes.byref(c), -1, d) == 0
+    assert L.bsf_filter_batched(ctypes.byref(c), -1, d, ws, need, None, 0) == bsf.E_INVALID
+    assert L.bsf_filter_batched(ctypes.byref(c), 2, None, ws, need, None, 0) == bsf.E_INVALID
+    assert L.bsf_filter_batched(ctypes.byref(c), 2, d, None, need, None, 0) == bsf.E_INVALID
+    # a NULL pointer or a short pitch on a non-empty image
+    bad = _descs(shapes)
+    bad[1].out = 0
+    assert L.bsf_filter_batched(ctypes.byref(c), 2, bad, ws, need, None, 0) == bsf.E_INVALID
+    bad = _descs(shapes)
+    bad[0].pitch = 51
+    assert L.bsf_filter_batched(ctypes.byref(c), 2, bad, ws, need, None, 0) == bsf.E_INVALID
+    # an image too large for the plan, and a bad configuration
+    big = _descs([(40, 52), (1 << 19, 4)])
+    assert L.bsf_filter_batched(ctypes.byref(c), 2, big, ws, need, None, 0) == bsf.E_INVALID
+    c_bad = bsf.Config(order=5).c()
+    assert L.bsf_filter_batched(ctypes.byref(c_bad), 2, d, ws, need, None, 0) == bsf.E_UNSUPPORTED
+    # workspace one byte short
+    assert L.bsf_filter_batched(ctypes.byref(c), 2, d, ws, need - 1, None, 0) == bsf.E_WORKSPACE
