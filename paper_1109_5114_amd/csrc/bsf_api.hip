@@ -151,6 +151,17 @@ GatherArgs gather_args(const Plan &p, const void *G, const float *steps, float *
                 break;
             }
     }
+    if (p.n_dirs == 4) {
+        static const int kCanon[4][2] = {{1, 0}, {0, 1}, {1, 1}, {1, -1}};
+        int found = 0;
+        for (int c = 0; c < 4; ++c)
+            for (int k = 0; k < 4; ++k)
+                if (p.dx[k] == kCanon[c][0] && p.dy[k] == kCanon[c][1]) {
+                    a.canon_plane[c] = k;
+                    ++found;
+                }
+        a.canon = found == 4 ? 1 : 0;
+    }
     for (int kk = 0; kk < p.n_dirs; ++kk) {
         const int k = perm[kk];
         for (int q = 0; q < p.order; ++q) {

@@ -117,6 +117,11 @@ struct GatherArgs {
     int M, order, tied, n_dirs;
     int32_t off[BSF_MAX_FACTORS];    // window offset (elements) of one lattice step along factor j
     int32_t plane[BSF_MAX_FACTORS];  // step plane of factor j
+    // Four directions that are exactly (1,0), (0,1), (1,1), (1,-1) in some
+    // order: canon = 1 and canon_plane[k] is the step plane of the k-th of
+    // those (the cluster-box kernels address taps in that fixed frame).
+    int32_t canon;
+    int32_t canon_plane[4];
 };
 bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st);
 // Arguments of the gather for one image (bsf_api.hip).

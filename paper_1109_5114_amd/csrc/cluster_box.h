@@ -1,0 +1,117 @@
+// Cluster boxes of the tied order-2 filter along the four directions
+// u_0 = (1,0), u_1 = (0,1), u_2 = (1,1), u_3 = (1,-1) (Section 1.1 with the
+// box factors of Table 1 used twice per direction).
+//
+// Along u_k the nine taps of a pixel (Alg. 3 step 3, squared difference
+// operator) lie in three clusters of three consecutive lattice points,
+//     T = 2R + {0,1,2},   M = -2 + {0,1,2},   B = -2R - 4 + {0,1,2},
+// with R = floor((s-1)/2) of the pixel's step.  Picking one cluster per
+// direction (a combination; 81 in all) leaves 3^4 taps that sit at
+// anchor + (q0 + q2 + q3, q1 + q2 - q3), q in {0,1,2}^4: a 7 x 7 patch with
+// 37 distinct points, where anchor = x + sum_k base_k u_k.  Over a tile of
+// pixels the anchors move with the pixel and with 2 (R - R') along u_k, so a
+// combination of a 16 x 16 tile reaches one small box of the running-sum
+// window.  The gather stages that box in LDS and reads it at static offsets;
+// the adjoint accumulates into it and adds it to the window once.
+//
+// The tensor of the 81 exact integer values J[o0][o1][o2][o3] (o = aa, ab,
+// bb per direction; the order-2 operators
+//     aa = T0 - 2 M1 + B2,   ab = T1 - M0 - M2 + B1,   bb = T2 - 2 M1 + B0)
+// is the sum over the combinations of their sub-patch, mapped per direction:
+// a T tap q feeds o = q, a B tap q feeds o = 2 - q, M1 feeds aa and bb with
+// weight 2 and M0, M2 feed ab; every M tap is negative, so the sign of a whole
+// combination is (-1)^(number of M clusters).
+#pragma once
+
+#include "bsf_common.h"
+
+namespace bsf {
+namespace cbox {
+
+constexpr int kTile = 16;                 // tile side, pixels
+constexpr int kPitch = 64;                // LDS box row pitch, elements
+constexpr int kRows = 48;                 // LDS box rows
+constexpr int kElems = kPitch * kRows;    // 24 KiB of int64
+constexpr int kCombos = 81;
+constexpr int kEven = 41;                 // combinations with an even number of M clusters
+
+// Cluster of direction k in combination C: 0 = T, 1 = M, 2 = B.
+__host__ __device__ constexpr int cl(int C, int k) {
+    return k == 0 ? C % 3 : k == 1 ? (C / 3) % 3 : k == 2 ? (C / 9) % 3 : (C / 27) % 3;
+}
+__host__ __device__ constexpr int n_m(int C) {
+    return (cl(C, 0) == 1) + (cl(C, 1) == 1) + (cl(C, 2) == 1) + (cl(C, 3) == 1);
+}
+// The I-th combination: those with an even number of M clusters first.
+__host__ __device__ constexpr int order_at(int I) {
+    int seen = 0;
+    for (int parity = 0; parity < 2; ++parity)
+        for (int C = 0; C < kCombos; ++C)
+            if ((n_m(C) & 1) == parity) {
+                if (seen == I) return C;
+                ++seen;
+            }
+    return -1;
+}
+
+// Per direction, a combination's sub-patch is reduced to "rows" r: a T or B
+// cluster keeps its three taps (r = q); an M cluster has two, r = 0 for M1
+// (feeding aa and bb, doubled) and r = 1 for M0 + M2 (feeding ab).
+__host__ __device__ constexpr int n_rows(int c) { return c == 1 ? 2 : 3; }
+__host__ __device__ constexpr int n_sub(int c, int r) { return (c == 1 && r == 1) ? 2 : 1; }
+__host__ __device__ constexpr int sub_q(int c, int r, int i) { return c == 1 ? (r == 0 ? 1 : 2 * i) : r; }
+__host__ __device__ constexpr int n_out(int c, int r) { return (c == 1 && r == 0) ? 2 : 1; }
+__host__ __device__ constexpr int out_o(int c, int r, int j) {
+    return c == 0 ? r : c == 2 ? 2 - r : (r == 0 ? 2 * j : 1);
+}
+__host__ __device__ constexpr int doubled(int c, int r) { return (c == 1 && r == 0) ? 1 : 0; }
+__host__ __device__ constexpr int jidx(int o0, int o1, int o2, int o3) { return ((o0 * 3 + o1) * 3 + o2) * 3 + o3; }
+
+// LDS element offset of sub-tap q from the pixel's base (the patch row Y = -2).
+__host__ __device__ constexpr int sub_elem(int q0, int q1, int q2, int q3) {
+    return (q0 + q2 + q3) + kPitch * (q1 + q2 - q3 + 2);
+}
+
+__device__ __forceinline__ int base_of(int c, int R) { return c == 0 ? 2 * R : c == 1 ? -2 : -2 * R - 4; }
+
+// Box of combination C for a tile whose active pixels span [x_lo, x_hi] x
+// [y_lo, y_hi] with R_k in [Rlo_k, Rhi_k]: image coordinates (ox, oy) of box
+// element (0, 0), width and height.
+struct Box {
+    int ox, oy, bw, bh;
+};
+
+template <int C>
+__device__ __forceinline__ Box box_of(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4], const int Rhi[4]) {
+    int bmin[4], bmax[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = cl(C, k);
+        bmin[k] = c == 0 ? 2 * Rlo[k] : c == 1 ? -2 : -2 * Rhi[k] - 4;
+        bmax[k] = c == 0 ? 2 * Rhi[k] : c == 1 ? -2 : -2 * Rlo[k] - 4;
+    }
+    const int ax_min = x_lo + bmin[0] + bmin[2] + bmin[3], ax_max = x_hi + bmax[0] + bmax[2] + bmax[3];
+    const int ay_min = y_lo + bmin[1] + bmin[2] - bmax[3], ay_max = y_hi + bmax[1] + bmax[2] - bmin[3];
+    return Box{ax_min, ay_min - 2, ax_max - ax_min + 7, ay_max - ay_min + 7};
+}
+
+// LDS element of the pixel's patch row Y = -2, column X = 0.
+template <int C>
+__device__ __forceinline__ int pixel_base(int x, int y, const int R[4], const Box &b) {
+    const int b0 = base_of(cl(C, 0), R[0]), b1 = base_of(cl(C, 1), R[1]);
+    const int b2 = base_of(cl(C, 2), R[2]), b3 = base_of(cl(C, 3), R[3]);
+    const int ax = x + b0 + b2 + b3, ay = y + b1 + b2 - b3;
+    return (ay - 2 - b.oy) * kPitch + (ax - b.ox);
+}
+
+// Largest box over the combinations (all clusters T or B) fits the LDS box.
+__device__ __forceinline__ bool boxes_fit(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4],
+                                          const int Rhi[4]) {
+    const int d0 = Rhi[0] - Rlo[0], d1 = Rhi[1] - Rlo[1], d2 = Rhi[2] - Rlo[2], d3 = Rhi[3] - Rlo[3];
+    const int w = (x_hi - x_lo) + 7 + 2 * (d0 + d2 + d3);
+    const int h = (y_hi - y_lo) + 7 + 2 * (d1 + d2 + d3);
+    return w <= kPitch && h <= kRows;
+}
+
+}  // namespace cbox
+}  // namespace bsf

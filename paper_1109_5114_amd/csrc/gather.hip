@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "bsf_common.h"
+#include "cluster_box.h"
 
 namespace bsf {
 namespace {
@@ -475,19 +476,14 @@ __device__ __forceinline__ double contract_fp(const int64_t acc[27], const doubl
     return r;
 }
 
-// Direction 0 is outermost: its taps are visited in an order that finishes
-// one operator at a time, so only the 27 values J[a0][.][.][.] of the current
-// operator a0 are live:
+// One pixel of the tied order-2 four-direction filter, taps read straight
+// from the window.  Direction 0 is outermost: its taps are visited in an order
+// that finishes one operator at a time, so only the 27 values J[a0][.][.][.] of
+// the current operator a0 are live:
 //   aa: -2 M1, + T0, + B2;   bb: -2 M1, + T2, + B0;   ab: -(M0 + M2), + T1, + B1
-// (M1 is visited twice, 10 steps in all).  WAVES bounds the registers so that
-// that many wavefronts fit on a SIMD; WX is the wavefront's pixel width.
-template <bool CONTIG, int WAVES, int WX, bool BATCH>
-__global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, const GatherArgs *__restrict__ table,
-                                                            const int64_t *__restrict__ prefix, int B) {
-    GatherArgs a;
-    int64_t bx, by, x, y;
-    if (!tile_of_block<BATCH>(one, table, prefix, B, WX, 256 / WX, a, bx, by)) return;
-    if (!pixel_wx<WX>(a, bx, by, x, y)) return;
+// (M1 is visited twice, 10 steps in all).
+template <bool CONTIG>
+__device__ __forceinline__ void t2n4_pixel(const GatherArgs &a, int64_t x, int64_t y) {
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const char *Gb = static_cast<const char *>(a.G);
     const uint32_t base = (uint32_t)(((y + a.pad_top) * a.Wp + (x + a.pad_left)) * 8);
@@ -557,6 +553,241 @@ __global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, cons
     }
 }
 
+// WAVES bounds the registers so that that many wavefronts fit on a SIMD; WX
+// is the wavefront's pixel width.
+template <bool CONTIG, int WAVES, int WX, bool BATCH>
+__global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, const GatherArgs *__restrict__ table,
+                                                            const int64_t *__restrict__ prefix, int B) {
+    GatherArgs a;
+    int64_t bx, by, x, y;
+    if (!tile_of_block<BATCH>(one, table, prefix, B, WX, 256 / WX, a, bx, by)) return;
+    if (!pixel_wx<WX>(a, bx, by, x, y)) return;
+    t2n4_pixel<CONTIG>(a, x, y);
+}
+
+// ----------------------------------------------------------------------------
+// Tied order-2 filter along (1,0), (0,1), (1,1), (1,-1) from LDS cluster boxes.
+// A 16 x 16 tile visits the 81 cluster combinations; for each it stages the
+// combination's box of the window in LDS with row-contiguous loads, and every
+// pixel reads its 37 distinct sub-patch points at static offsets from its
+// anchor and adds them into the 81 exact values J.  Combinations with an even
+// number of M clusters come first; J is then negated once, so the odd ones
+// (whose taps are all negative) are added too, and the FP64 combination
+// negates the result back.  A tile whose step range would not fit the LDS box
+// falls back to reading its taps from the window.
+// ----------------------------------------------------------------------------
+template <int C>
+__device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, uint64_t J[81]) {
+    using namespace cbox;
+    constexpr int c0 = cl(C, 0), c1 = cl(C, 1), c2 = cl(C, 2), c3 = cl(C, 3);
+#pragma unroll
+    for (int r0 = 0; r0 < n_rows(c0); ++r0)
+#pragma unroll
+        for (int r1 = 0; r1 < n_rows(c1); ++r1)
+#pragma unroll
+            for (int r2 = 0; r2 < n_rows(c2); ++r2)
+#pragma unroll
+                for (int r3 = 0; r3 < n_rows(c3); ++r3) {
+                    uint64_t v = 0;
+#pragma unroll
+                    for (int i0 = 0; i0 < n_sub(c0, r0); ++i0)
+#pragma unroll
+                        for (int i1 = 0; i1 < n_sub(c1, r1); ++i1)
+#pragma unroll
+                            for (int i2 = 0; i2 < n_sub(c2, r2); ++i2)
+#pragma unroll
+                                for (int i3 = 0; i3 < n_sub(c3, r3); ++i3)
+                                    v += p[sub_elem(sub_q(c0, r0, i0), sub_q(c1, r1, i1), sub_q(c2, r2, i2),
+                                                    sub_q(c3, r3, i3))];
+                    const int sh = doubled(c0, r0) + doubled(c1, r1) + doubled(c2, r2) + doubled(c3, r3);
+#pragma unroll
+                    for (int j0 = 0; j0 < n_out(c0, r0); ++j0)
+#pragma unroll
+                        for (int j1 = 0; j1 < n_out(c1, r1); ++j1)
+#pragma unroll
+                            for (int j2 = 0; j2 < n_out(c2, r2); ++j2)
+#pragma unroll
+                                for (int j3 = 0; j3 < n_out(c3, r3); ++j3)
+                                    J[jidx(out_o(c0, r0, j0), out_o(c1, r1, j1), out_o(c2, r2, j2),
+                                           out_o(c3, r3, j3))] += v << sh;
+                }
+}
+
+// Start copying box b of the window into the LDS buffer dst (rows of kPitch
+// elements) with LDS-direct loads: each wavefront instruction moves 32
+// consecutive int64 of one row as 64 dwords, lanes past the box width idle.
+// Completion is waited for (vmcnt) before the barrier that publishes the box.
+__device__ __forceinline__ void box_stage_async(const GatherArgs &a, uint64_t *__restrict__ dst,
+                                                const cbox::Box &b) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t *__restrict__ G = static_cast<const uint64_t *>(a.G);
+    const int64_t r0 = b.oy + a.pad_top, c0 = b.ox + a.pad_left;
+    const int e_lo = lane >> 1, word = lane & 1;
+    for (int r = w; r < b.bh; r += 4) {
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(G + (r0 + r) * a.Wp + c0) + word;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = 32 * h + e_lo;
+            if (e < b.bw)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(row + 2 * e),
+                    (__attribute__((address_space(3))) void *)(dst + r * cbox::kPitch + 32 * h), 4, 0, 0);
+        }
+    }
+}
+
+struct BoxTile {
+    int x, y;              // pixel
+    int R[4];
+    int x_lo, x_hi, y_lo, y_hi;
+    int Rlo[4], Rhi[4];
+};
+
+// Combination I reads buffer I % 2 while combination I + 1 is copied into the
+// other one; one barrier per combination publishes the next box and frees the
+// current one.
+template <int I>
+__device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__restrict__ s_box, bool active,
+                                            const BoxTile &t, uint64_t J[81]) {
+    constexpr int C = cbox::order_at(I);
+    const cbox::Box b = cbox::box_of<C>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi);
+    if constexpr (I + 1 < cbox::kCombos) {
+        constexpr int Cn = cbox::order_at(I + 1);
+        const cbox::Box bn = cbox::box_of<Cn>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi);
+        box_stage_async(a, s_box + ((I + 1) & 1) * cbox::kElems, bn);
+    }
+    if constexpr (I == cbox::kEven) {
+#pragma unroll
+        for (int q = 0; q < 81; ++q) J[q] = 0 - J[q];
+    }
+    if (active) box_fwd_combo<C>(s_box + (I & 1) * cbox::kElems + cbox::pixel_base<C>(t.x, t.y, t.R, b), J);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if constexpr (I + 1 < cbox::kCombos) box_fwd_all<I + 1>(a, s_box, active, t, J);
+}
+
+__device__ __forceinline__ double contract81(const double Jd[81], const double w0[3], const double w1[3],
+                                             const double w2[3], const double w3[3]) {
+    double r = 0.0;
+#pragma unroll
+    for (int o0 = 0; o0 < 3; ++o0) {
+        double r1 = 0.0;
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int o2 = 0; o2 < 3; ++o2) {
+                double r3 = 0.0;
+#pragma unroll
+                for (int o3 = 0; o3 < 3; ++o3) r3 += w3[o3] * Jd[cbox::jidx(o0, o1, o2, o3)];
+                r2 += w2[o2] * r3;
+            }
+            r1 += w1[o1] * r2;
+        }
+        r += w0[o0] * r1;
+    }
+    return r;
+}
+
+// Tile-wide min / max of R per direction over the active pixels.
+__device__ __forceinline__ void tile_R_range(const int R[4], bool active, int Rlo[4], int Rhi[4]) {
+    __shared__ int s_red[4][8];
+    int lo[4], hi[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lo[k] = active ? R[k] : 0x7fffffff;
+        hi[k] = active ? R[k] : -0x7fffffff;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lo[k] = min(lo[k], __shfl_xor(lo[k], d, 64));
+            hi[k] = max(hi[k], __shfl_xor(hi[k], d, 64));
+        }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s_red[w][k] = lo[k];
+            s_red[w][4 + k] = hi[k];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int l = min(min(s_red[0][k], s_red[1][k]), min(s_red[2][k], s_red[3][k]));
+        const int h = max(max(s_red[0][4 + k], s_red[1][4 + k]), max(s_red[2][4 + k], s_red[3][4 + k]));
+        Rlo[k] = __builtin_amdgcn_readfirstlane(l);
+        Rhi[k] = __builtin_amdgcn_readfirstlane(h);
+    }
+}
+
+template <bool BATCH>
+__global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, const GatherArgs *__restrict__ table,
+                                                            const int64_t *__restrict__ prefix, int B) {
+    __shared__ uint64_t s_box[2 * cbox::kElems];
+    GatherArgs a;
+    int64_t bx, by;
+    if (!tile_of_block<BATCH>(one, table, prefix, B, cbox::kTile, cbox::kTile, a, bx, by)) return;
+    BoxTile t;
+    t.x = (int)(bx * cbox::kTile) + (threadIdx.x & 15);
+    t.y = (int)(by * cbox::kTile) + (threadIdx.x >> 4);
+    const bool active = t.x < a.W && t.y < a.H;
+    const int64_t HW = a.H * a.W, idx = (int64_t)t.y * a.W + t.x;
+    float ph[4], sk[4];
+    double den = 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float s = active ? clamp_step(a.steps[a.canon_plane[k] * HW + idx], a.max_step) : 1.0f;
+        const float tt = (s - 1.0f) * 0.5f;
+        const float Rf = floorf(tt);
+        t.R[k] = (int)Rf;
+        ph[k] = tt - Rf;
+        sk[k] = s;
+        den *= (double)s * (double)s;
+    }
+    tile_R_range(t.R, active, t.Rlo, t.Rhi);
+    t.x_lo = (int)(bx * cbox::kTile);
+    t.y_lo = (int)(by * cbox::kTile);
+    t.x_hi = (int)min((int64_t)t.x_lo + cbox::kTile - 1, a.W - 1);
+    t.y_hi = (int)min((int64_t)t.y_lo + cbox::kTile - 1, a.H - 1);
+    if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi)) {
+        if (active) {
+            if (a.off[6] == 1) t2n4_pixel<true>(a, t.x, t.y);
+            else t2n4_pixel<false>(a, t.x, t.y);
+        }
+        return;
+    }
+    uint64_t J[81];
+#pragma unroll
+    for (int q = 0; q < 81; ++q) J[q] = 0;
+    box_stage_async(a, s_box, cbox::box_of<cbox::order_at(0)>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi));
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    box_fwd_all<0>(a, s_box, active, t, J);
+    if (!active) return;
+    double Jd[81];
+#pragma unroll
+    for (int q = 0; q < 81; ++q) Jd[q] = -(double)(int64_t)J[q];
+    double w[4][3], dw[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) phase_weights(ph[k], w[k], dw[k]);
+    const int F = a.status[ST_F_USED];
+    const double outv = ldexp_neg(contract81(Jd, w[0], w[1], w[2], w[3]), F) / den;
+    if (a.out) a.out[idx] = (float)outv;
+    if (a.dsteps) {
+        double d[4];
+        d[0] = contract81(Jd, dw[0], w[1], w[2], w[3]);
+        d[1] = contract81(Jd, w[0], dw[1], w[2], w[3]);
+        d[2] = contract81(Jd, w[0], w[1], dw[2], w[3]);
+        d[3] = contract81(Jd, w[0], w[1], w[2], dw[3]);
+        // d phi / d s = 1/2, and each step enters prod s twice
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            a.dsteps[a.canon_plane[k] * HW + idx] = (float)(0.5 * ldexp_neg(d[k], F) / den - 2.0 * outv / sk[k]);
+    }
+}
+
 // Plain FP64 counterpart: FP64 running sums and FP64 tap weights
 //   T0:(1-p)^2 T1:2p(1-p) T2:p^2 M0:-2p(1-p) M1:-2((1-p)^2+p^2) M2:-2p(1-p) B0:p^2 B1:2p(1-p) B2:(1-p)^2
 __device__ __forceinline__ void offsets9(int32_t R, int32_t off, int32_t o[9]) {
@@ -614,7 +845,7 @@ __global__ __launch_bounds__(256) void k_gather_t2n4_fp64(GatherArgs one, const 
 
 // Pixel-tile shape of the kernel run_gather picks for a plan.
 struct GatherShape {
-    int kind;  // 0 int, 1 generic real, 2 tied order-2 exact, 3 tied order-2 fp64
+    int kind;  // 0 int, 1 generic real, 2 tied order-2 exact, 3 tied order-2 fp64, 4 cluster boxes
     int tile_w, tile_h;
 };
 
@@ -625,6 +856,8 @@ GatherShape gather_shape(const Plan &p, const GatherArgs &a) {
     } else if (p.n_dirs == 4 && p.order == 2 && p.tied && p.Hp * p.Wp * 8 < (int64_t(1) << 32)) {
         if (p.arith == BSF_ARITH_FP64) {
             s.kind = 3;
+        } else if (a.canon) {
+            s.kind = 4;
         } else {
             s.kind = 2;
             const bool contig = a.off[6] == 1;
@@ -658,6 +891,8 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
         }
     } else if (s.kind == 3) {
         hipLaunchKernelGGL((k_gather_t2n4_fp64<BATCH>), grid, block, 0, st, one, table, prefix, B);
+    } else if (s.kind == 4) {
+        hipLaunchKernelGGL((k_gather_t2n4_box<BATCH>), grid, block, 0, st, one, table, prefix, B);
     } else if (s.kind == 2) {
         const bool contig = one.off[6] == 1;
         if (!contig) hipLaunchKernelGGL((k_gather_t2n4<false, 2, 16, BATCH>), grid, block, 0, st, one, table, prefix, B);
