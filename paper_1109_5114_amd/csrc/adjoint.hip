@@ -16,6 +16,7 @@
 // out exact; Fg is chosen from max |g| with 3 bits of headroom for the column
 // sums of the kernels.  The only error is the rounding of omega_J.
 #include "bsf_common.h"
+#include "cluster_box.h"
 
 namespace bsf {
 namespace {
@@ -98,9 +99,8 @@ __device__ __forceinline__ int64_t expand3(int p, const int64_t v[3]) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_adj_scatter_t2n4(AdjointArgs a) {
-    int64_t x, y;
-    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+// One pixel's scatter straight into the window (global atomics).
+__device__ __forceinline__ void adj_t2n4_pixel(const AdjointArgs &a, int64_t x, int64_t y) {
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const float g = a.gout[idx];
     if (!(g != 0.0f)) return;  // zero (or NaN) upstream gradient scatters nothing
@@ -164,6 +164,203 @@ __global__ __launch_bounds__(256) void k_adj_scatter_t2n4(AdjointArgs a) {
             }
         }
     }
+}
+
+
+__global__ __launch_bounds__(256) void k_adj_scatter_t2n4(AdjointArgs a) {
+    int64_t x, y;
+    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    adj_t2n4_pixel(a, x, y);
+}
+
+// ----------------------------------------------------------------------------
+// The same scatter through LDS cluster boxes (directions (1,0), (0,1), (1,1),
+// (1,-1)).  A 16 x 16 tile visits the 81 cluster combinations; for each,
+// every pixel adds its sub-patch weights, summed per distinct point, into the
+// combination's box in LDS, and after one barrier the box is added to the
+// window with row-contiguous atomics and cleared.  Two LDS boxes alternate,
+// so the flush of one combination and the accumulation of the next need a
+// single barrier.  The weight of sub-tap q is the sum of omega over the
+// operators it feeds: one per T or B direction, aa + bb (doubled) for M1 and
+// ab for M0 and M2; combinations with an odd number of M clusters are
+// negative, which a single negation of omega between the two parity groups
+// takes care of.
+// ----------------------------------------------------------------------------
+// Weight of sub-tap Q of combination C: the sum of omega over the operators
+// it feeds, doubled once per M1 it contains.
+template <int C, int Q>
+__device__ __forceinline__ uint64_t sub_weight(const uint64_t W[81]) {
+    using namespace cbox;
+    constexpr int c0 = cl(C, 0), c1 = cl(C, 1), c2 = cl(C, 2), c3 = cl(C, 3);
+    constexpr int q0 = Q % 3, q1 = (Q / 3) % 3, q2 = (Q / 9) % 3, q3 = Q / 27;
+    constexpr int n0 = (c0 == 1 && q0 == 1) ? 2 : 1, n1 = (c1 == 1 && q1 == 1) ? 2 : 1;
+    constexpr int n2 = (c2 == 1 && q2 == 1) ? 2 : 1, n3 = (c3 == 1 && q3 == 1) ? 2 : 1;
+    constexpr int sh = (n0 - 1) + (n1 - 1) + (n2 - 1) + (n3 - 1);
+    uint64_t u = 0;
+#pragma unroll
+    for (int j0 = 0; j0 < n0; ++j0)
+#pragma unroll
+        for (int j1 = 0; j1 < n1; ++j1)
+#pragma unroll
+            for (int j2 = 0; j2 < n2; ++j2)
+#pragma unroll
+                for (int j3 = 0; j3 < n3; ++j3) {
+                    const int o0 = c0 == 0 ? q0 : c0 == 2 ? 2 - q0 : (q0 == 1 ? 2 * j0 : 1);
+                    const int o1 = c1 == 0 ? q1 : c1 == 2 ? 2 - q1 : (q1 == 1 ? 2 * j1 : 1);
+                    const int o2 = c2 == 0 ? q2 : c2 == 2 ? 2 - q2 : (q2 == 1 ? 2 * j2 : 1);
+                    const int o3 = c3 == 0 ? q3 : c3 == 2 ? 2 - q3 : (q3 == 1 ? 2 * j3 : 1);
+                    u += W[jidx(o0, o1, o2, o3)];
+                }
+    return u << sh;
+}
+
+template <int C, int P, int I>
+__device__ __forceinline__ uint64_t point_weight(const uint64_t W[81]) {
+    constexpr int Q = cbox::kPatch.q[P][I];
+    if constexpr (I + 1 < cbox::kPatch.count[P]) return sub_weight<C, Q>(W) + point_weight<C, P, I + 1>(W);
+    else return sub_weight<C, Q>(W);
+}
+
+// One LDS atomic per distinct patch point, points in row order.
+template <int C, int P>
+__device__ __forceinline__ void box_adj_points(uint64_t *__restrict__ p, const uint64_t W[81]) {
+    if constexpr (cbox::kPatch.count[P] > 0)
+        __hip_atomic_fetch_add(p + cbox::point_elem(P), point_weight<C, P, 0>(W), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    if constexpr (P + 1 < 49) box_adj_points<C, P + 1>(p, W);
+}
+
+struct AdjTile {
+    int x, y;
+    int R[4];
+    int x_lo, x_hi, y_lo, y_hi;
+    int Rlo[4], Rhi[4];
+};
+
+// Add box b of LDS buffer src to the window and clear it.
+__device__ __forceinline__ void box_flush(const AdjointArgs &a, uint64_t *__restrict__ src, const cbox::Box &b) {
+    const int64_t r0 = b.oy + a.pad_top, c0 = b.ox + a.pad_left;
+    const int n = b.bh * cbox::kPitch;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int r = i / cbox::kPitch, c = i % cbox::kPitch;
+        if (c < b.bw) {
+            const uint64_t v = src[i];
+            if (v != 0) {
+                atomic_add_i64(a.Ghat + (r0 + r) * a.Wp + c0 + c, (int64_t)v);
+                src[i] = 0;
+            }
+        }
+    }
+}
+
+template <int I>
+__device__ __forceinline__ void box_adj_all(const AdjointArgs &a, uint64_t *__restrict__ s_box, bool active,
+                                            const AdjTile &t, uint64_t W[81]) {
+    constexpr int C = cbox::order_at(I);
+    const cbox::Box b = cbox::box_of<C>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi);
+    if constexpr (I == cbox::kEven) {
+#pragma unroll
+        for (int q = 0; q < 81; ++q) W[q] = 0 - W[q];
+    }
+    // sums of weights are formed again in every combination rather than kept
+    // alive across them (which would not fit the registers)
+#pragma unroll
+    for (int q = 0; q < 81; ++q) asm volatile("" : "+v"(W[q]));
+    uint64_t *buf = s_box + (I & 1) * cbox::kElems;
+    if (active) box_adj_points<C, 0>(buf + cbox::pixel_base<C>(t.x, t.y, t.R, b), W);
+    __syncthreads();  // box complete; the other buffer was flushed before the previous barrier
+    box_flush(a, buf, b);
+    if constexpr (I + 1 < cbox::kCombos) box_adj_all<I + 1>(a, s_box, active, t, W);
+}
+
+__global__ __launch_bounds__(256, 2) void k_adj_scatter_t2n4_box(AdjointArgs a) {
+    __shared__ uint64_t s_box[2 * cbox::kElems];
+    const int64_t bx = blockIdx.x, by = blockIdx.y;
+    AdjTile t;
+    t.x = (int)(bx * cbox::kTile) + (threadIdx.x & 15);
+    t.y = (int)(by * cbox::kTile) + (threadIdx.x >> 4);
+    const bool inside = t.x < a.W && t.y < a.H;
+    const int64_t HW = a.H * a.W, idx = (int64_t)t.y * a.W + t.x;
+    const float g = inside ? a.gout[idx] : 0.0f;
+    const bool active = inside && (g != 0.0f);  // zero (or NaN) upstream gradient scatters nothing
+    float ph[4];
+    double den = 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float s = inside ? clamp_step(a.steps[a.canon_plane[k] * HW + idx], a.max_step) : 1.0f;
+        const float tt = (s - 1.0f) * 0.5f;
+        const float Rf = floorf(tt);
+        t.R[k] = (int)Rf;
+        ph[k] = tt - Rf;
+        den *= (double)s * (double)s;
+    }
+    // tile-wide R range over the pixels that scatter
+    __shared__ int s_red[4][8];
+    {
+        int lo[4], hi[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lo[k] = active ? t.R[k] : 0x7fffffff;
+            hi[k] = active ? t.R[k] : -0x7fffffff;
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                lo[k] = min(lo[k], __shfl_xor(lo[k], d, 64));
+                hi[k] = max(hi[k], __shfl_xor(hi[k], d, 64));
+            }
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s_red[w][k] = lo[k];
+                s_red[w][4 + k] = hi[k];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            t.Rlo[k] = __builtin_amdgcn_readfirstlane(
+                min(min(s_red[0][k], s_red[1][k]), min(s_red[2][k], s_red[3][k])));
+            t.Rhi[k] = __builtin_amdgcn_readfirstlane(
+                max(max(s_red[0][4 + k], s_red[1][4 + k]), max(s_red[2][4 + k], s_red[3][4 + k])));
+        }
+    }
+    if (t.Rlo[0] > t.Rhi[0]) return;  // nothing in the tile scatters
+    t.x_lo = (int)(bx * cbox::kTile);
+    t.y_lo = (int)(by * cbox::kTile);
+    t.x_hi = (int)min((int64_t)t.x_lo + cbox::kTile - 1, a.W - 1);
+    t.y_hi = (int)min((int64_t)t.y_lo + cbox::kTile - 1, a.H - 1);
+    if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi)) {
+        if (active) adj_t2n4_pixel(a, t.x, t.y);
+        return;
+    }
+    // fixed-point weights of the 81 operator combinations
+    uint64_t W[81];
+    {
+        double w[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double pk = (double)ph[k], qk = 1.0 - pk;
+            w[k][0] = qk * qk;
+            w[k][1] = 2.0 * pk * qk;
+            w[k][2] = pk * pk;
+        }
+        const double fb = active ? __builtin_ldexp((double)g / den, a.status[ST_FG]) : 0.0;
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+            for (int o2 = 0; o2 < 3; ++o2)
+#pragma unroll
+                for (int o3 = 0; o3 < 3; ++o3) {
+                    const double r = fb * w[1][o1] * w[2][o2] * w[3][o3];
+#pragma unroll
+                    for (int o0 = 0; o0 < 3; ++o0) W[cbox::jidx(o0, o1, o2, o3)] = (uint64_t)fixed(r * w[0][o0]);
+                }
+    }
+    for (int i = threadIdx.x; i < 2 * cbox::kElems; i += 256) s_box[i] = 0;
+    __syncthreads();
+    box_adj_all<0>(a, s_box, active, t, W);
 }
 
 // Any factor count: per factor the narrow and wide boxes, 2^M box choices e
@@ -245,7 +442,9 @@ bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *sta
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)fb), dim3(256), 0, st, a.Ghat, n);
     BSF_HIP_CHECK(hipGetLastError());
     dim3 grid((unsigned)((p.W + kTile - 1) / kTile), (unsigned)((p.H + kTile - 1) / kTile));
-    if (p.n_dirs == 4 && p.order == 2 && p.tied)
+    if (p.n_dirs == 4 && p.order == 2 && p.tied && a.canon)
+        hipLaunchKernelGGL(k_adj_scatter_t2n4_box, grid, dim3(256), 0, st, a);
+    else if (p.n_dirs == 4 && p.order == 2 && p.tied)
         hipLaunchKernelGGL(k_adj_scatter_t2n4, grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(k_adj_scatter_generic, grid, dim3(256), 0, st, a);

@@ -363,6 +363,8 @@ bsf_status bsf_filter_backward(const bsf_config *cfg, int64_t H, int64_t W, cons
         a.n_dirs = p.n_dirs;
         memcpy(a.off, ga.off, sizeof(a.off));
         memcpy(a.plane, ga.plane, sizeof(a.plane));
+        a.canon = ga.canon;
+        memcpy(a.canon_plane, ga.canon_plane, sizeof(a.canon_plane));
         r = run_adjoint_scatter(p, a, L.status, st);
         if (r != BSF_OK) return r;
         r = run_preintegrate_transpose(p, L.G, L.aux, st);

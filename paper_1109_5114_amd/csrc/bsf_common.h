@@ -168,6 +168,8 @@ struct AdjointArgs {
     int M, order, tied, n_dirs;
     int32_t off[BSF_MAX_FACTORS];
     int32_t plane[BSF_MAX_FACTORS];
+    int32_t canon;            // as in GatherArgs
+    int32_t canon_plane[4];
 };
 bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *status, hipStream_t st);
 bsf_status run_adjoint_finish(const Plan &p, const int64_t *Ghat, const int32_t *status, float *grad_img,

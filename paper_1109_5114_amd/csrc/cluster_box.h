@@ -72,6 +72,24 @@ __host__ __device__ constexpr int sub_elem(int q0, int q1, int q2, int q3) {
     return (q0 + q2 + q3) + kPitch * (q1 + q2 - q3 + 2);
 }
 
+// The sub-taps q (index q0 + 3 q1 + 9 q2 + 27 q3) at each of the 7 x 7 patch
+// points P = X + 7 (Y + 2); 37 points are hit, by at most five sub-taps.
+struct PatchTable {
+    int count[49];
+    int q[49][5];
+};
+__host__ __device__ constexpr PatchTable make_patch_table() {
+    PatchTable t{};
+    for (int q = 0; q < 81; ++q) {
+        const int q0 = q % 3, q1 = (q / 3) % 3, q2 = (q / 9) % 3, q3 = q / 27;
+        const int P = (q0 + q2 + q3) + 7 * (q1 + q2 - q3 + 2);
+        t.q[P][t.count[P]++] = q;
+    }
+    return t;
+}
+constexpr PatchTable kPatch = make_patch_table();
+__host__ __device__ constexpr int point_elem(int P) { return (P % 7) + kPitch * (P / 7); }
+
 __device__ __forceinline__ int base_of(int c, int R) { return c == 0 ? 2 * R : c == 1 ? -2 : -2 * R - 4; }
 
 // Box of combination C for a tile whose active pixels span [x_lo, x_hi] x

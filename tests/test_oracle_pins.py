@@ -409,6 +409,63 @@ def test_running_sums_and_signed_taps_reproduce_filter_int(order):
             assert _taps_int(G, pads, fdirs, svec, x, y) == num[y, x]
 
 
+def _table1():
+    """Rows of tests/golden/table1_fd_mesh.txt: (cx[4], cy[4], sign)."""
+    import os
+    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_fd_mesh.txt")
+    for line in open(path):
+        line = line.split("#")[0].split()
+        if not line:
+            continue
+        v = [int(t) for t in line[1:9]]
+        rows.append((v[:4], v[4:], +1 if line[9] == "+" else -1))
+    return rows
+
+
+def test_table1_mesh_and_shifts_reproduce_the_filter():
+    """Table 1 (finite-difference mesh of beta'_a in Alg. 3) with the shifts of
+    eq. (shifts): the 16 printed taps, read at x - tau on running sums that
+    accumulate from the +u side along the four directions of beta' (the
+    directions are those of the single-scale rows 1, 2, 4 and 8), give the
+    oracle's integer filter for odd scales a' (tau is then a lattice point).
+    This pins the oracle's directions, step units (a' = a / sqrt 5), centring
+    and signs against the printed table."""
+    rows = _table1()
+    assert len(rows) == 16
+    dirs = []
+    for k, i in enumerate((1, 2, 4, 8)):
+        cx, cy, _ = rows[i]
+        dirs.append((cx[k], cy[k]))
+    assert dirs == [(2, 1), (1, 2), (-1, 2), (-2, 1)]
+    # row i carries the scales of the binary digits of i, sign (-1)^(digits)
+    for i, (cx, cy, sg) in enumerate(rows):
+        used = [k for k in range(4) if cx[k] or cy[k]]
+        assert used == [k for k in range(4) if i >> k & 1]
+        assert sg == (-1) ** len(used)
+    rng = np.random.default_rng(21)
+    H, W = 11, 14
+    img = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    steps = (2 * rng.integers(0, 3, size=(4, H, W)) + 1).astype(np.float32)   # a' in {1, 3, 5}
+    pad = 24
+    G = O.preintegrate(img, [(-dx, -dy) for dx, dy in dirs], 1, 0, (pad, pad, pad, pad))
+    _, num, den = O.filter(img, dirs, 1, True, O.INT, steps, want_int=True)
+    for y in range(H):
+        for x in range(W):
+            a = [int(steps[k, y, x]) for k in range(4)]
+            t1 = (2 * a[0] + a[1] - a[2] - 2 * a[3]) // 2
+            t2 = (a[0] + 2 * a[1] + 2 * a[2] + a[3] - 6) // 2
+            acc = 0
+            for cx, cy, sg in rows:
+                px = x - t1 + sum(c * v for c, v in zip(cx, a))
+                py = y - t2 + sum(c * v for c, v in zip(cy, a))
+                acc += sg * int(G[py + pad, px + pad])
+            acc %= 1 << 64
+            acc = acc - (1 << 64) if acc >= 1 << 63 else acc
+            assert acc == num[y, x], (y, x, a)
+            assert den[y, x] == np.prod(a)
+
+
 def test_running_sums_and_interpolated_taps_reproduce_filter_real():
     """Continuous steps: reading the running sum linearly between lattice
     points along each u_j (the one-direction restriction of eq.
