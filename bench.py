@@ -31,6 +31,25 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
 INT64_OPS_PER_PIXEL = (729 + 243 + 81 + 27) * 8
 
 
+def measured_traffic():
+    """HBM bytes per launch of the tap kernel from the committed counter runs
+    (profiles/traffic.json), or None when the kernel source has changed since
+    they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for name in rec.get("sources", []):
+        with open(os.path.join(ROOT, name), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("sha256"):
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -49,6 +68,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="images in the batched workload (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed region, one device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the filter would shard by "
@@ -252,6 +273,13 @@ def main():
                "sample": "%d random pixels of the 4096x4096 order-2 workload, %.1f s" % (n, dt)}
         log("cpu oracle %d px in %.1f s" % (n, dt))
 
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     ops = INT64_OPS_PER_PIXEL * H * W
     achieved = ops / (apply_ms / 1e3) / 1e12
     res = {
@@ -272,7 +300,7 @@ def main():
                    "H": H, "W": W, "order": 2, "n_dirs": 4, "max_step": d["max_step"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": measured_traffic(),
                      "kernel": "per-pixel taps (forward_apply)", "kernel_ms": apply_ms},
         "cpu_baseline": cpu,
         "stages_ms": {"prepare": prep_ms, "apply": apply_ms, "wall_per_step": wall},

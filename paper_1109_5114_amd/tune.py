@@ -100,8 +100,11 @@ def tune(cfg: Config, H: int, W: int, device="cuda", reps: int = 3, cache: Optio
         ws = Workspace(g.workspace_bytes, device)
         forward_prepare(cfg, img, steps, ws)
         out = torch.empty((H, W), dtype=torch.float32, device=device)
+        # the block width only shapes the tied order-2 kernel for direction sets
+        # other than (1,0), (0,1), (1,1), (1,-1); those use the cluster-box kernel
+        canonical = sorted(map(tuple, cfg.dirs)) == sorted(((1, 0), (0, 1), (1, 1), (1, -1)))
         uses_wx = cfg.mode != STEPS_INT and cfg.order == 2 and cfg.tied and cfg.n_dirs == 4 \
-            and cfg.arith == ARITH_EXACT
+            and cfg.arith == ARITH_EXACT and not canonical
         for wx in (gather_wx if uses_wx else (old[0],)):
             set_tuning(wx, best_tl)
             forward_apply(cfg, 3, steps, ws, out)    # warm-up
