@@ -257,7 +257,7 @@ template <int I>
 __device__ __forceinline__ void box_adj_all(const AdjointArgs &a, uint64_t *__restrict__ s_box, bool active,
                                             const AdjTile &t, uint64_t W[81]) {
     constexpr int C = cbox::order_at(I);
-    const cbox::Box b = cbox::box_of<C>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi);
+    const cbox::Box b = cbox::box_of<C>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, (int)a.pad_left);
     if constexpr (I == cbox::kEven) {
 #pragma unroll
         for (int q = 0; q < 81; ++q) W[q] = 0 - W[q];

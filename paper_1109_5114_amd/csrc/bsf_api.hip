@@ -96,7 +96,9 @@ bsf_status make_plan(const bsf_config *cfg, int64_t H, int64_t W, Plan *p) {
     p->pad_top = top;
     p->pad_bottom = bottom;
     p->pad_left = left;
-    int64_t Wp = W + left + right;
+    // one spare column past the rightmost tap: the gather copies boxes of the
+    // window in aligned pairs of elements
+    int64_t Wp = W + left + right + 1;
     Wp = (Wp + 15) / 16 * 16;
     p->pad_right = Wp - W - left;
     p->Wp = Wp;

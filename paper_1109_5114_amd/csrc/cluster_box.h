@@ -94,13 +94,17 @@ __device__ __forceinline__ int base_of(int c, int R) { return c == 0 ? 2 * R : c
 
 // Box of combination C for a tile whose active pixels span [x_lo, x_hi] x
 // [y_lo, y_hi] with R_k in [Rlo_k, Rhi_k]: image coordinates (ox, oy) of box
-// element (0, 0), width and height.
+// element (0, 0), width and height.  The box starts on an even window column
+// (widened by one column on the left when needed), so that it can be copied
+// in aligned pairs of elements; a pair may then end one column past the box,
+// which the window's spare right column keeps inside the window.
 struct Box {
     int ox, oy, bw, bh;
 };
 
 template <int C>
-__device__ __forceinline__ Box box_of(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4], const int Rhi[4]) {
+__device__ __forceinline__ Box box_of(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4], const int Rhi[4],
+                                      int pad_left) {
     int bmin[4], bmax[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -110,7 +114,8 @@ __device__ __forceinline__ Box box_of(int x_lo, int x_hi, int y_lo, int y_hi, co
     }
     const int ax_min = x_lo + bmin[0] + bmin[2] + bmin[3], ax_max = x_hi + bmax[0] + bmax[2] + bmax[3];
     const int ay_min = y_lo + bmin[1] + bmin[2] - bmax[3], ay_max = y_hi + bmax[1] + bmax[2] - bmin[3];
-    return Box{ax_min, ay_min - 2, ax_max - ax_min + 7, ay_max - ay_min + 7};
+    const int odd = (ax_min + pad_left) & 1;
+    return Box{ax_min - odd, ay_min - 2, ax_max - ax_min + 7 + odd, ay_max - ay_min + 7};
 }
 
 // LDS element of the pixel's patch row Y = -2, column X = 0.
@@ -122,11 +127,12 @@ __device__ __forceinline__ int pixel_base(int x, int y, const int R[4], const Bo
     return (ay - 2 - b.oy) * kPitch + (ax - b.ox);
 }
 
-// Largest box over the combinations (all clusters T or B) fits the LDS box.
+// Largest box over the combinations (all clusters T or B, one column of
+// alignment) fits the LDS box.
 __device__ __forceinline__ bool boxes_fit(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4],
                                           const int Rhi[4]) {
     const int d0 = Rhi[0] - Rlo[0], d1 = Rhi[1] - Rlo[1], d2 = Rhi[2] - Rlo[2], d3 = Rhi[3] - Rlo[3];
-    const int w = (x_hi - x_lo) + 7 + 2 * (d0 + d2 + d3);
+    const int w = (x_hi - x_lo) + 8 + 2 * (d0 + d2 + d3);
     const int h = (y_hi - y_lo) + 7 + 2 * (d1 + d2 + d3);
     return w <= kPitch && h <= kRows;
 }

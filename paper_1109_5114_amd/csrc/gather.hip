@@ -576,6 +576,18 @@ __global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, cons
 // negates the result back.  A tile whose step range would not fit the LDS box
 // falls back to reading its taps from the window.
 // ----------------------------------------------------------------------------
+// acc += v << sh as one v_lshl_add_u64 (sh <= 4), also when the same shifted
+// value feeds two accumulators (the compiler would shift once and add twice).
+__device__ __forceinline__ void shl_add(uint64_t &acc, uint64_t v, int sh) {
+    switch (sh) {
+    case 0: acc += v; break;
+    case 1: asm("v_lshl_add_u64 %0, %1, 1, %2" : "=v"(acc) : "v"(v), "v"(acc)); break;
+    case 2: asm("v_lshl_add_u64 %0, %1, 2, %2" : "=v"(acc) : "v"(v), "v"(acc)); break;
+    case 3: asm("v_lshl_add_u64 %0, %1, 3, %2" : "=v"(acc) : "v"(v), "v"(acc)); break;
+    default: asm("v_lshl_add_u64 %0, %1, 4, %2" : "=v"(acc) : "v"(v), "v"(acc)); break;
+    }
+}
+
 template <int C>
 __device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, uint64_t J[81]) {
     using namespace cbox;
@@ -608,31 +620,31 @@ __device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, ui
                             for (int j2 = 0; j2 < n_out(c2, r2); ++j2)
 #pragma unroll
                                 for (int j3 = 0; j3 < n_out(c3, r3); ++j3)
-                                    J[jidx(out_o(c0, r0, j0), out_o(c1, r1, j1), out_o(c2, r2, j2),
-                                           out_o(c3, r3, j3))] += v << sh;
+                                    shl_add(J[jidx(out_o(c0, r0, j0), out_o(c1, r1, j1), out_o(c2, r2, j2),
+                                                   out_o(c3, r3, j3))],
+                                            v, sh);
                 }
 }
 
 // Start copying box b of the window into the LDS buffer dst (rows of kPitch
-// elements) with LDS-direct loads: each wavefront instruction moves 32
-// consecutive int64 of one row as 64 dwords, lanes past the box width idle.
-// Completion is waited for (vmcnt) before the barrier that publishes the box.
+// elements) with LDS-direct loads: one instruction moves two box rows as 64
+// aligned pairs of elements (lane l: row l / 32, elements 2 (l % 32) and the
+// next), the four wavefronts taking turns; lanes whose pair lies outside the
+// box idle.  Completion is waited for (vmcnt) before the barrier that
+// publishes the box.
 __device__ __forceinline__ void box_stage_async(const GatherArgs &a, uint64_t *__restrict__ dst,
                                                 const cbox::Box &b) {
+    static_assert(cbox::kPitch == 64, "two box rows per 64-lane copy");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint64_t *__restrict__ G = static_cast<const uint64_t *>(a.G);
-    const int64_t r0 = b.oy + a.pad_top, c0 = b.ox + a.pad_left;
-    const int e_lo = lane >> 1, word = lane & 1;
-    for (int r = w; r < b.bh; r += 4) {
-        const uint32_t *row = reinterpret_cast<const uint32_t *>(G + (r0 + r) * a.Wp + c0) + word;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = 32 * h + e_lo;
-            if (e < b.bw)
-                __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void *)(row + 2 * e),
-                    (__attribute__((address_space(3))) void *)(dst + r * cbox::kPitch + 32 * h), 4, 0, 0);
-        }
+    const int half = lane >> 5, col = 2 * (lane & 31);
+    const bool col_in = col < b.bw;
+    const uint64_t *__restrict__ src =
+        static_cast<const uint64_t *>(a.G) + (int64_t)(b.oy + a.pad_top + half) * a.Wp + (b.ox + a.pad_left + col);
+    for (int r = 2 * w; r < b.bh; r += 8) {
+        if (col_in && r + half < b.bh)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(src + (int64_t)r * a.Wp),
+                                             (__attribute__((address_space(3))) void *)(dst + r * cbox::kPitch), 16, 0,
+                                             0);
     }
 }
 
@@ -641,6 +653,7 @@ struct BoxTile {
     int R[4];
     int x_lo, x_hi, y_lo, y_hi;
     int Rlo[4], Rhi[4];
+    int pad_left;
 };
 
 // Combination I reads buffer I % 2 while combination I + 1 is copied into the
@@ -650,10 +663,10 @@ template <int I>
 __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__restrict__ s_box, bool active,
                                             const BoxTile &t, uint64_t J[81]) {
     constexpr int C = cbox::order_at(I);
-    const cbox::Box b = cbox::box_of<C>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi);
+    const cbox::Box b = cbox::box_of<C>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left);
     if constexpr (I + 1 < cbox::kCombos) {
         constexpr int Cn = cbox::order_at(I + 1);
-        const cbox::Box bn = cbox::box_of<Cn>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi);
+        const cbox::Box bn = cbox::box_of<Cn>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left);
         box_stage_async(a, s_box + ((I + 1) & 1) * cbox::kElems, bn);
     }
     if constexpr (I == cbox::kEven) {
@@ -751,6 +764,7 @@ __global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, cons
     t.y_lo = (int)(by * cbox::kTile);
     t.x_hi = (int)min((int64_t)t.x_lo + cbox::kTile - 1, a.W - 1);
     t.y_hi = (int)min((int64_t)t.y_lo + cbox::kTile - 1, a.H - 1);
+    t.pad_left = (int)a.pad_left;
     if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi)) {
         if (active) {
             if (a.off[6] == 1) t2n4_pixel<true>(a, t.x, t.y);
@@ -761,7 +775,8 @@ __global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, cons
     uint64_t J[81];
 #pragma unroll
     for (int q = 0; q < 81; ++q) J[q] = 0;
-    box_stage_async(a, s_box, cbox::box_of<cbox::order_at(0)>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi));
+    box_stage_async(a, s_box,
+                    cbox::box_of<cbox::order_at(0)>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left));
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     box_fwd_all<0>(a, s_box, active, t, J);
