@@ -275,7 +275,10 @@ __device__ __forceinline__ void box_adj_all(const AdjointArgs &a, uint64_t *__re
 
 __global__ __launch_bounds__(256, 2) void k_adj_scatter_t2n4_box(AdjointArgs a) {
     __shared__ uint64_t s_box[2 * cbox::kElems];
-    const int64_t bx = blockIdx.x, by = blockIdx.y;
+    const int64_t tiles_x = (a.W + cbox::kTile - 1) / cbox::kTile, tiles_y = (a.H + cbox::kTile - 1) / cbox::kTile;
+    const int64_t item = xcd_item(blockIdx.x, tiles_x * tiles_y);
+    if (item >= tiles_x * tiles_y) return;
+    const int64_t bx = item % tiles_x, by = item / tiles_x;
     AdjTile t;
     t.x = (int)(bx * cbox::kTile) + (threadIdx.x & 15);
     t.y = (int)(by * cbox::kTile) + (threadIdx.x >> 4);
@@ -443,7 +446,8 @@ bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *sta
     BSF_HIP_CHECK(hipGetLastError());
     dim3 grid((unsigned)((p.W + kTile - 1) / kTile), (unsigned)((p.H + kTile - 1) / kTile));
     if (p.n_dirs == 4 && p.order == 2 && p.tied && a.canon)
-        hipLaunchKernelGGL(k_adj_scatter_t2n4_box, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_adj_scatter_t2n4_box, dim3((unsigned)xcd_grid((int64_t)grid.x * grid.y)), dim3(256), 0,
+                           st, a);
     else if (p.n_dirs == 4 && p.order == 2 && p.tied)
         hipLaunchKernelGGL(k_adj_scatter_t2n4, grid, dim3(256), 0, st, a);
     else

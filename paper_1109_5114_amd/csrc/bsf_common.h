@@ -79,6 +79,18 @@ struct ScanJob {
     int dir;  // row passes: +1 forward, -1 reversed
 };
 
+// Workgroups are handed to the 8 XCDs of the device in turn, each XCD with its
+// own L2.  Block b of a grid padded to a multiple of 8 takes item
+// (b % 8) * per + b / 8 (per = ceil(n / 8)): every XCD works through one
+// contiguous range of items, so neighbouring tiles, whose boxes of the window
+// overlap, meet in the same L2.  Items >= n are idle.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n) {
+    const int64_t per = (n + kXcds - 1) / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+inline int64_t xcd_grid(int64_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
+
 // Job b of a batched launch owns the work items [prefix[b], prefix[b+1]).
 __device__ __forceinline__ int find_job(const int64_t *__restrict__ prefix, int B, int64_t item) {
     int lo = 0, hi = B - 1;

@@ -50,6 +50,32 @@ __device__ __forceinline__ bool tile_of_block(const GatherArgs &one, const Gathe
     return true;
 }
 
+// As tile_of_block, for a 1-D grid of xcd_grid(tiles) blocks in XCD order.
+template <bool BATCH>
+__device__ __forceinline__ bool tile_of_block_xcd(const GatherArgs &one, const GatherArgs *__restrict__ table,
+                                                  const int64_t *__restrict__ prefix, int B, int tile_w, int tile_h,
+                                                  GatherArgs &a, int64_t &bx, int64_t &by) {
+    if constexpr (BATCH) {
+        const int64_t total = prefix[B];
+        const int64_t gi = xcd_item(blockIdx.x, total);
+        if (gi >= total) return false;
+        const int b = find_job(prefix, B, gi);
+        a = table[b];
+        const int64_t item = gi - prefix[b];
+        const int64_t tiles_x = (a.W + tile_w - 1) / tile_w;
+        bx = item % tiles_x;
+        by = item / tiles_x;
+    } else {
+        a = one;
+        const int64_t tiles_x = (a.W + tile_w - 1) / tile_w, tiles_y = (a.H + tile_h - 1) / tile_h;
+        const int64_t item = xcd_item(blockIdx.x, tiles_x * tiles_y);
+        if (item >= tiles_x * tiles_y) return false;
+        bx = item % tiles_x;
+        by = item / tiles_x;
+    }
+    return true;
+}
+
 // 16 x 16 tile, each wavefront an 8 x 8 block.
 __device__ __forceinline__ bool pixel_16x16(const GatherArgs &a, int64_t bx, int64_t by, int64_t &x, int64_t &y) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -741,7 +767,7 @@ __global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, cons
     __shared__ uint64_t s_box[2 * cbox::kElems];
     GatherArgs a;
     int64_t bx, by;
-    if (!tile_of_block<BATCH>(one, table, prefix, B, cbox::kTile, cbox::kTile, a, bx, by)) return;
+    if (!tile_of_block_xcd<BATCH>(one, table, prefix, B, cbox::kTile, cbox::kTile, a, bx, by)) return;
     BoxTile t;
     t.x = (int)(bx * cbox::kTile) + (threadIdx.x & 15);
     t.y = (int)(by * cbox::kTile) + (threadIdx.x >> 4);
@@ -889,7 +915,11 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
                          int64_t total_tiles, hipStream_t st) {
     const GatherShape s = gather_shape(p, one);
     dim3 grid;
-    if (BATCH) {
+    if (s.kind == 4) {
+        const int64_t tiles = BATCH ? total_tiles
+                                    : ((p.W + s.tile_w - 1) / s.tile_w) * ((p.H + s.tile_h - 1) / s.tile_h);
+        grid = dim3((unsigned)xcd_grid(tiles));
+    } else if (BATCH) {
         grid = dim3((unsigned)total_tiles);
     } else {
         grid = dim3((unsigned)((p.W + s.tile_w - 1) / s.tile_w), (unsigned)((p.H + s.tile_h - 1) / s.tile_h));
