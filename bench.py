@@ -23,9 +23,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpixels/s and HBM GB/s, fwd and fwd+adjoint, 4096^2 N=4 order-2 vs plain path"
 HBM_PEAK_GBS = 8000.0
-# int64 adds per second: 256 CUs x 64 lanes x 2.4 GHz 32-bit VALU operations,
-# two of which (add, add-with-carry) make one 64-bit add
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 2 / 1e12
+# int64 adds per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 64-bit
+# add (v_lshl_add_u64) per lane per cycle
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # exact separable contraction of the 9^4 taps of one pixel: 729 + 243 + 81 + 27
 # groups of nine values reduced to three operator outputs, 8 int64 adds each
 INT64_OPS_PER_PIXEL = (729 + 243 + 81 + 27) * 8
@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="images in the batched workload (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--int-size", type=int, default=2048, help="integer-step uint8 workload side (0: skip)")
+    ap.add_argument("--int-steps", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, one device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -204,6 +206,52 @@ def main():
               "steps": args.adjoint_steps, "grad_steps_max_rel_err_vs_oracle": gerr}
         log("fwd+adjoint %.3f ms (fwd %.3f, bwd %.3f)" % (t_fa, np.mean(fwd_ms), np.mean(bwd_ms)))
 
+    # ---- integer steps on a uint8 image: exact int64 numerator and prod s
+    integer = None
+    if args.int_size > 0:
+        d3 = WL.workload3(args.int_size, args.int_size)
+        H3, W3 = d3["img"].shape
+        cfg3 = bsf.Config(dirs=d3["dirs"], order=1, tied=True, mode=bsf.STEPS_INT, max_step=d3["max_step"])
+        img3 = torch.from_numpy(d3["img"]).to(dev)
+        steps3 = torch.from_numpy(d3["steps"]).to(dev)
+        ws3 = bsf.Workspace(bsf.plan(cfg3, H3, W3).workspace_bytes, dev)
+        out3 = torch.empty((H3, W3), dtype=torch.float32, device=dev)
+        num3 = torch.empty((H3, W3), dtype=torch.int64, device=dev)
+        den3 = torch.empty_like(num3)
+
+        def step3():
+            bsf.forward_prepare(cfg3, img3, steps3, ws3)
+            bsf.forward_apply(cfg3, bsf.U8, steps3, ws3, out3, num=num3, den=den3)
+
+        step3()
+        torch.cuda.synchronize()
+        ev3 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.int_steps)]
+        for k in range(args.int_steps):
+            ev3[k][0].record(stream)
+            bsf.forward_prepare(cfg3, img3, steps3, ws3)
+            ev3[k][1].record(stream)
+            bsf.forward_apply(cfg3, bsf.U8, steps3, ws3, out3, num=num3, den=den3)
+            ev3[k][2].record(stream)
+        torch.cuda.synchronize()
+        p3 = float(np.mean([e[0].elapsed_time(e[1]) for e in ev3]))
+        a3 = float(np.mean([e[1].elapsed_time(e[2]) for e in ev3]))
+        pix3 = rng.integers(0, H3 * W3, 64)
+        _, rnum, rden = O.filter(d3["img"], d3["dirs"], 1, True, O.INT, d3["steps"], pix=pix3, want_int=True)
+        exact = bool(np.array_equal(num3.cpu().numpy().reshape(-1)[pix3], rnum)
+                     and np.array_equal(den3.cpu().numpy().reshape(-1)[pix3], rden))
+        # algorithmic HBM bytes of the tap kernel per pixel: four FP32 step
+        # planes, the running-sum window once, FP32 out, int64 numerator and
+        # product of steps
+        g3 = bsf.plan(cfg3, H3, W3)
+        tap_bytes = H3 * W3 * (16 + 4 + 8 + 8) + g3.g_bytes
+        integer = {"workload": d3["name"], "ms_per_step": p3 + a3, "prepare_ms": p3, "apply_ms": a3,
+                   "value": H3 * W3 / ((p3 + a3) / 1e3) / 1e6, "unit": "Mpixels/s",
+                   "apply_hbm_gbs": tap_bytes / (a3 / 1e3) / 1e9,
+                   "apply_hbm_frac": tap_bytes / (a3 / 1e3) / 1e9 / HBM_PEAK_GBS,
+                   "bit_exact_sampled": exact, "pixels_checked": int(len(pix3))}
+        log("integer %dx%d: %.3f ms (prepare %.3f, apply %.3f), exact=%s" % (H3, W3, p3 + a3, p3, a3, exact))
+        del ws3, img3, steps3, out3, num3, den3
+
     # ---- batched: images of uneven sizes, each stage one launch over the batch, replayed as a graph
     batched = None
     if args.batch > 0:
@@ -312,6 +360,7 @@ def main():
                        "max_abs_err_vs_oracle": plain_abs, "max_rel_err_vs_oracle": plain_rel},
         "fwd_adjoint": fa,
         "batched": batched,
+        "integer_steps": integer,
         "tuning": None if tuning is None else {k: tuning[k] for k in ("gather_wx", "line_tl")},
     }
     print(json.dumps(res))

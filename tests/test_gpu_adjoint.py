@@ -162,3 +162,30 @@ def test_differentiation_workload_crop_finite_differences():
                          window=(max(0, x0 - m), min(W, x1 + m), max(0, y0 - m), min(H, y1 + m)),
                          want_steps=False)
     assert_grad_close(gi[y0:y1, x0:x1], rgi[y0:y1, x0:x1], what="grad_img crop")
+
+
+@pytest.mark.slow
+def test_full_size_image_gradient_crops():
+    """The 4096 x 4096 order-2 workload (steps up to 48) through the forward
+    and the adjoint exactly as the benchmark runs them: the image gradient on
+    three 24 x 24 crops (centre, top-left corner, bottom-right edge) against the
+    FP64 oracle's adjoint restricted to the output pixels that reach each crop,
+    and the step gradient at sampled pixels against the oracle's derivative."""
+    note("adjoint 4096 crops")
+    d = WL.workload2(4096, 4096)
+    img, steps = d["img"], d["steps"]
+    g = np.random.default_rng(11095114 + 99).standard_normal(img.shape, dtype=np.float32)
+    cfg = bsf.Config(order=2, max_step=d["max_step"])
+    out, gi, gs, ds = gpu_grads(cfg, img, steps, g)
+    H, W = img.shape
+    R = int((d["max_step"] - 1) // 2)
+    reach = 2 * (R + 2) * 3 + 2
+    for (y0, x0, n) in ((2040, 2040, 24), (0, 0, 24), (H - 24, W - 24, 24)):
+        win = (max(0, x0 - reach), min(W, x0 + n + reach), max(0, y0 - reach), min(H, y0 + n + reach))
+        rgi, _ = O.grad_real(img, DIRS4, 2, True, steps, g, window=win, want_steps=False)
+        assert_grad_close(gi[y0:y0 + n, x0:x0 + n], rgi[y0:y0 + n, x0:x0 + n], rel_norm=1e-6, rel_max=1e-5,
+                          what="grad_img crop %d,%d" % (y0, x0))
+    rng = np.random.default_rng(53)
+    pix = np.concatenate([rng.integers(0, H * W, 40), [0, W - 1, H * W - 1]])
+    _, rgs = O.grad_real(img, DIRS4, 2, True, steps, g, pix=pix, want_img=False)
+    assert_grad_close(gs.reshape(4, -1)[:, pix].T, rgs, what="grad_steps sampled")

@@ -152,3 +152,26 @@ def test_tuning_does_not_change_results(wx, tl):
     np.testing.assert_array_equal(G, G_ref)
     np.testing.assert_array_equal(got, ref)
     np.testing.assert_array_equal(got_b, ref)
+
+
+@pytest.mark.slow
+def test_full_isotropic_batch_matches_oracle():
+    """The whole batched workload (64 images with sides 128..2048, isotropic
+    order-2 steps, sigma in [1, 16]) in one graph-captured call, as the
+    benchmark runs it: sampled pixels of every image against the FP64 oracle,
+    borders included."""
+    note("workload4 full vs oracle")
+    d = WL.workload4()
+    cfg = cfg_of(d)
+    imgs = [it["img"] for it in d["items"]]
+    steps = [it["steps"] for it in d["items"]]
+    batch = bsf.Batch(cfg, to_dev(imgs), to_dev(steps))
+    outs = [o.cpu().numpy() for o in batch.run(use_graph=True)]
+    flags, F, _ = batch.ws.status()
+    assert flags == 0
+    rng = np.random.default_rng(83)
+    for b, (im, st, out) in enumerate(zip(imgs, steps, outs)):
+        H, W = im.shape
+        pix = np.unique(np.concatenate([rng.integers(0, H * W, 12), [0, W - 1, (H - 1) * W, H * W - 1]]))
+        ref = O.filter(im, d["dirs"], 2, True, O.REAL, st, pix=pix)
+        assert_close(out.reshape(-1)[pix], ref, F, what="image %d" % b)
