@@ -235,6 +235,7 @@ struct AdjTile {
     int R[4];
     int x_lo, x_hi, y_lo, y_hi;
     int Rlo[4], Rhi[4];
+    uint32_t packed;       // cbox::pack_state: all the loop needs of the pixel
 };
 
 // Add box b of LDS buffer src to the window and clear it.
@@ -267,7 +268,7 @@ __device__ __forceinline__ void box_adj_all(const AdjointArgs &a, uint64_t *__re
 #pragma unroll
     for (int q = 0; q < 81; ++q) asm volatile("" : "+v"(W[q]));
     uint64_t *buf = s_box + (I & 1) * cbox::kElems;
-    if (active) box_adj_points<C, 0>(buf + cbox::pixel_base<C>(t.x, t.y, t.R, b), W);
+    if (active) box_adj_points<C, 0>(buf + cbox::packed_base<C>(t.packed, t.x_lo, t.y_lo, t.Rlo, b), W);
     __syncthreads();  // box complete; the other buffer was flushed before the previous barrier
     box_flush(a, buf, b);
     if constexpr (I + 1 < cbox::kCombos) box_adj_all<I + 1>(a, s_box, active, t, W);
@@ -338,6 +339,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_scatter_t2n4_box(AdjointArgs a) 
         if (active) adj_t2n4_pixel(a, t.x, t.y);
         return;
     }
+    t.packed = cbox::pack_state(threadIdx.x & 15, threadIdx.x >> 4, t.R, t.Rlo, active);
     // fixed-point weights of the 81 operator combinations
     uint64_t W[81];
     {

@@ -127,6 +127,44 @@ __device__ __forceinline__ int pixel_base(int x, int y, const int R[4], const Bo
     return (ay - 2 - b.oy) * kPitch + (ax - b.ox);
 }
 
+// The pixel's state through a combination loop, in one register: bits 0-9
+// hold tx + 64 ty (its position in the 16 x 16 tile), then R_k - Rlo_k in five
+// bits per direction (at most 20 whenever the boxes fit).  Inactive pixels
+// store zero differences.
+__device__ __forceinline__ uint32_t pack_state(int tx, int ty, const int R[4], const int Rlo[4], bool active) {
+    uint32_t st = (uint32_t)(tx + kPitch * ty);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) st |= (uint32_t)(active ? R[k] - Rlo[k] : 0) << (10 + 5 * k);
+    return st;
+}
+
+// pixel_base from the packed state: 64 ty + tx + sum_k coef_k b_k with
+// coef = (1, 64, 65, -63) the LDS offsets of u = (1,0), (0,1), (1,1), (1,-1)
+// and b_k = 2 R_k (T), -2 (M), -2 R_k - 4 (B); the tile-uniform part is
+// formed once per combination.
+template <int C>
+__device__ __forceinline__ int packed_base(uint32_t st, int x_lo, int y_lo, const int Rlo[4], const Box &b) {
+    static_assert(kPitch == 64, "coefficients assume a 64-element pitch");
+    constexpr int coef[4] = {1, 64, 65, -63};
+    int v = (int)(st & 1023u);
+    int sc = kPitch * (y_lo - 2 - b.oy) + (x_lo - b.ox);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = cl(C, k);
+        const int dR = (int)((st >> (10 + 5 * k)) & 31u);
+        if (c == 0) {
+            v += 2 * coef[k] * dR;
+            sc += 2 * coef[k] * Rlo[k];
+        } else if (c == 2) {
+            v -= 2 * coef[k] * dR;
+            sc += coef[k] * (-2 * Rlo[k] - 4);
+        } else {
+            sc += -2 * coef[k];
+        }
+    }
+    return v + sc;
+}
+
 // Largest box over the combinations (all clusters T or B, one column of
 // alignment) fits the LDS box.
 __device__ __forceinline__ bool boxes_fit(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4],

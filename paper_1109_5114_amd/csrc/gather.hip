@@ -680,7 +680,10 @@ struct BoxTile {
     int x_lo, x_hi, y_lo, y_hi;
     int Rlo[4], Rhi[4];
     int pad_left;
+    uint32_t packed;       // cbox::pack_state
 };
+
+
 
 // Combination I reads buffer I % 2 while combination I + 1 is copied into the
 // other one; one barrier per combination publishes the next box and frees the
@@ -699,7 +702,7 @@ __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__res
 #pragma unroll
         for (int q = 0; q < 81; ++q) J[q] = 0 - J[q];
     }
-    if (active) box_fwd_combo<C>(s_box + (I & 1) * cbox::kElems + cbox::pixel_base<C>(t.x, t.y, t.R, b), J);
+    if (active) box_fwd_combo<C>(s_box + (I & 1) * cbox::kElems + cbox::packed_base<C>(t.packed, t.x_lo, t.y_lo, t.Rlo, b), J);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if constexpr (I + 1 < cbox::kCombos) box_fwd_all<I + 1>(a, s_box, active, t, J);
@@ -772,18 +775,13 @@ __global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, cons
     t.x = (int)(bx * cbox::kTile) + (threadIdx.x & 15);
     t.y = (int)(by * cbox::kTile) + (threadIdx.x >> 4);
     const bool active = t.x < a.W && t.y < a.H;
-    const int64_t HW = a.H * a.W, idx = (int64_t)t.y * a.W + t.x;
-    float ph[4], sk[4];
-    double den = 1.0;
+    {
+        const int64_t HW = a.H * a.W, idx = (int64_t)t.y * a.W + t.x;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float s = active ? clamp_step(a.steps[a.canon_plane[k] * HW + idx], a.max_step) : 1.0f;
-        const float tt = (s - 1.0f) * 0.5f;
-        const float Rf = floorf(tt);
-        t.R[k] = (int)Rf;
-        ph[k] = tt - Rf;
-        sk[k] = s;
-        den *= (double)s * (double)s;
+        for (int k = 0; k < 4; ++k) {
+            const float s = active ? clamp_step(a.steps[a.canon_plane[k] * HW + idx], a.max_step) : 1.0f;
+            t.R[k] = (int)floorf((s - 1.0f) * 0.5f);
+        }
     }
     tile_R_range(t.R, active, t.Rlo, t.Rhi);
     t.x_lo = (int)(bx * cbox::kTile);
@@ -791,6 +789,7 @@ __global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, cons
     t.x_hi = (int)min((int64_t)t.x_lo + cbox::kTile - 1, a.W - 1);
     t.y_hi = (int)min((int64_t)t.y_lo + cbox::kTile - 1, a.H - 1);
     t.pad_left = (int)a.pad_left;
+    t.packed = cbox::pack_state(threadIdx.x & 15, threadIdx.x >> 4, t.R, t.Rlo, active);
     if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi)) {
         if (active) {
             if (a.off[6] == 1) t2n4_pixel<true>(a, t.x, t.y);
@@ -806,7 +805,21 @@ __global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, cons
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     box_fwd_all<0>(a, s_box, active, t, J);
-    if (!active) return;
+    // the pixel's position and phases are formed again here rather than held
+    // through the loop
+    const int px = t.x_lo + (threadIdx.x & 15), py = t.y_lo + (threadIdx.x >> 4);
+    if (px >= a.W || py >= a.H) return;
+    const int64_t HW = a.H * a.W, idx = (int64_t)py * a.W + px;
+    float ph[4], sk[4];
+    double den = 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float s = clamp_step(a.steps[a.canon_plane[k] * HW + idx], a.max_step);
+        const float tt = (s - 1.0f) * 0.5f;
+        ph[k] = tt - floorf(tt);
+        sk[k] = s;
+        den *= (double)s * (double)s;
+    }
     double Jd[81];
 #pragma unroll
     for (int q = 0; q < 81; ++q) Jd[q] = -(double)(int64_t)J[q];
