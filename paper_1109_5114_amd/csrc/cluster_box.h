@@ -166,13 +166,13 @@ __device__ __forceinline__ int packed_base(uint32_t st, int x_lo, int y_lo, cons
 }
 
 // Largest box over the combinations (all clusters T or B, one column of
-// alignment) fits the LDS box.
+// alignment) fits an LDS box of the given number of rows.
 __device__ __forceinline__ bool boxes_fit(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4],
-                                          const int Rhi[4]) {
+                                          const int Rhi[4], int rows = kRows) {
     const int d0 = Rhi[0] - Rlo[0], d1 = Rhi[1] - Rlo[1], d2 = Rhi[2] - Rlo[2], d3 = Rhi[3] - Rlo[3];
     const int w = (x_hi - x_lo) + 8 + 2 * (d0 + d2 + d3);
     const int h = (y_hi - y_lo) + 7 + 2 * (d1 + d2 + d3);
-    return w <= kPitch && h <= kRows;
+    return w <= kPitch && h <= rows;
 }
 
 }  // namespace cbox

@@ -614,8 +614,23 @@ __device__ __forceinline__ void shl_add(uint64_t &acc, uint64_t v, int sh) {
     }
 }
 
+// Tile of the forward cluster-box kernel: kFwdTileW columns by kFwdTileH rows
+// of pixels, one wavefront per 16 x 4 block of them, and the LDS box rows it
+// stages.
+constexpr int kFwdTileW = 16;
+constexpr int kFwdTileH = 8;
+constexpr int kFwdWaves = (kFwdTileW / 16) * (kFwdTileH / 4);
+constexpr int kFwdRows = 32;
+constexpr int kFwdElems = cbox::kPitch * kFwdRows;
+static_assert(kFwdTileW % 16 == 0 && kFwdTileH % 4 == 0 && kFwdTileW + 64 * (kFwdTileH - 1) < 1024 &&
+                  kFwdRows % 2 == 0, "tile shape");
+// Position of thread i's pixel in the tile.
+__device__ __forceinline__ int fwd_tx(int i) { return 16 * ((i >> 6) % (kFwdTileW / 16)) + (i & 15); }
+__device__ __forceinline__ int fwd_ty(int i) { return 4 * ((i >> 6) / (kFwdTileW / 16)) + ((i >> 4) & 3); }
+
 template <int C>
-__device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, uint64_t J[81]) {
+__device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, const uint64_t *__restrict__ p_hi,
+                                              uint64_t J[81]) {
     using namespace cbox;
     constexpr int c0 = cl(C, 0), c1 = cl(C, 1), c2 = cl(C, 2), c3 = cl(C, 3);
 #pragma unroll
@@ -635,8 +650,11 @@ __device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, ui
                             for (int i2 = 0; i2 < n_sub(c2, r2); ++i2)
 #pragma unroll
                                 for (int i3 = 0; i3 < n_sub(c3, r3); ++i3)
-                                    v += p[sub_elem(sub_q(c0, r0, i0), sub_q(c1, r1, i1), sub_q(c2, r2, i2),
-                                                    sub_q(c3, r3, i3))];
+                                {
+                                    const int e = sub_elem(sub_q(c0, r0, i0), sub_q(c1, r1, i1),
+                                                               sub_q(c2, r2, i2), sub_q(c3, r3, i3));
+                                    v += e < 4 * kPitch ? p[e] : p_hi[e - 4 * kPitch];
+                                }
                     const int sh = doubled(c0, r0) + doubled(c1, r1) + doubled(c2, r2) + doubled(c3, r3);
 #pragma unroll
                     for (int j0 = 0; j0 < n_out(c0, r0); ++j0)
@@ -655,23 +673,33 @@ __device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, ui
 // Start copying box b of the window into the LDS buffer dst (rows of kPitch
 // elements) with LDS-direct loads: one instruction moves two box rows as 64
 // aligned pairs of elements (lane l: row l / 32, elements 2 (l % 32) and the
-// next), the four wavefronts taking turns; lanes whose pair lies outside the
-// box idle.  Completion is waited for (vmcnt) before the barrier that
-// publishes the box.
+// next), wavefront w taking the row pairs w, w + kFwdWaves, ...; lanes whose pair
+// lies right of the box idle, as do the second-row lanes of a last, unpaired
+// row.  The loop runs on wavefront-uniform values only: a pair's window row
+// and LDS row advance by scalar adds.  Completion is waited for (vmcnt)
+// before the barrier that publishes the box.
 __device__ __forceinline__ void box_stage_async(const GatherArgs &a, uint64_t *__restrict__ dst,
-                                                const cbox::Box &b) {
+                                                const cbox::Box &b, int w) {
     static_assert(cbox::kPitch == 64, "two box rows per 64-lane copy");
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int half = lane >> 5, col = 2 * (lane & 31);
-    const bool col_in = col < b.bw;
-    const uint64_t *__restrict__ src =
-        static_cast<const uint64_t *>(a.G) + (int64_t)(b.oy + a.pad_top + half) * a.Wp + (b.ox + a.pad_left + col);
-    for (int r = 2 * w; r < b.bh; r += 8) {
-        if (col_in && r + half < b.bh)
-            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(src + (int64_t)r * a.Wp),
-                                             (__attribute__((address_space(3))) void *)(dst + r * cbox::kPitch), 16, 0,
-                                             0);
-    }
+    const int lane = threadIdx.x & 63;
+    const int col = 2 * (lane & 31);
+    const bool upper = lane >= 32;
+    if (col >= b.bw) return;
+    const int64_t Wp = a.Wp;
+    const uint32_t lane_off = (uint32_t)(((upper ? Wp : 0) + col) * 8);
+    const char *__restrict__ row =
+        reinterpret_cast<const char *>(static_cast<const uint64_t *>(a.G) +
+                                       ((int64_t)(b.oy + a.pad_top + 2 * w) * Wp + (b.ox + a.pad_left)));
+    const int64_t row_step = 2 * kFwdWaves * Wp * 8;             // kFwdWaves pairs of window rows, bytes
+    uint64_t *l = dst + 2 * w * cbox::kPitch;
+    const int full = b.bh >> 1;                                  // pairs with both rows in the box
+    int pr = w;
+    for (; pr < full; pr += kFwdWaves, row += row_step, l += 2 * kFwdWaves * cbox::kPitch)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(row + lane_off),
+                                         (__attribute__((address_space(3))) void *)l, 16, 0, 0);
+    if ((b.bh & 1) && pr == full && !upper)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(row + lane_off),
+                                         (__attribute__((address_space(3))) void *)l, 16, 0, 0);
 }
 
 struct BoxTile {
@@ -680,6 +708,7 @@ struct BoxTile {
     int x_lo, x_hi, y_lo, y_hi;
     int Rlo[4], Rhi[4];
     int pad_left;
+    int wave;              // wavefront of the pixel in its workgroup (uniform)
     uint32_t packed;       // cbox::pack_state
 };
 
@@ -696,13 +725,18 @@ __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__res
     if constexpr (I + 1 < cbox::kCombos) {
         constexpr int Cn = cbox::order_at(I + 1);
         const cbox::Box bn = cbox::box_of<Cn>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left);
-        box_stage_async(a, s_box + ((I + 1) & 1) * cbox::kElems, bn);
+        box_stage_async(a, s_box + ((I + 1) & 1) * kFwdElems, bn, t.wave);
     }
     if constexpr (I == cbox::kEven) {
 #pragma unroll
         for (int q = 0; q < 81; ++q) J[q] = 0 - J[q];
     }
-    if (active) box_fwd_combo<C>(s_box + (I & 1) * cbox::kElems + cbox::packed_base<C>(t.packed, t.x_lo, t.y_lo, t.Rlo, b), J);
+    if (active) {
+        int base = (I & 1) * kFwdElems + cbox::packed_base<C>(t.packed, t.x_lo, t.y_lo, t.Rlo, b);
+        int base_hi = base + 4 * cbox::kPitch;
+        asm("" : "+v"(base), "+v"(base_hi));
+        box_fwd_combo<C>(s_box + base, s_box + base_hi, J);
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if constexpr (I + 1 < cbox::kCombos) box_fwd_all<I + 1>(a, s_box, active, t, J);
@@ -733,7 +767,7 @@ __device__ __forceinline__ double contract81(const double Jd[81], const double w
 
 // Tile-wide min / max of R per direction over the active pixels.
 __device__ __forceinline__ void tile_R_range(const int R[4], bool active, int Rlo[4], int Rhi[4]) {
-    __shared__ int s_red[4][8];
+    __shared__ int s_red[kFwdWaves][8];
     int lo[4], hi[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -757,23 +791,27 @@ __device__ __forceinline__ void tile_R_range(const int R[4], bool active, int Rl
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int l = min(min(s_red[0][k], s_red[1][k]), min(s_red[2][k], s_red[3][k]));
-        const int h = max(max(s_red[0][4 + k], s_red[1][4 + k]), max(s_red[2][4 + k], s_red[3][4 + k]));
+        int l = s_red[0][k], h = s_red[0][4 + k];
+#pragma unroll
+        for (int v = 1; v < kFwdWaves; ++v) {
+            l = min(l, s_red[v][k]);
+            h = max(h, s_red[v][4 + k]);
+        }
         Rlo[k] = __builtin_amdgcn_readfirstlane(l);
         Rhi[k] = __builtin_amdgcn_readfirstlane(h);
     }
 }
 
 template <bool BATCH>
-__global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, const GatherArgs *__restrict__ table,
-                                                            const int64_t *__restrict__ prefix, int B) {
-    __shared__ uint64_t s_box[2 * cbox::kElems];
+__global__ __launch_bounds__(64 * kFwdWaves, 2) void k_gather_t2n4_box(
+    GatherArgs one, const GatherArgs *__restrict__ table, const int64_t *__restrict__ prefix, int B) {
+    __shared__ uint64_t s_box[2 * kFwdElems];
     GatherArgs a;
     int64_t bx, by;
-    if (!tile_of_block_xcd<BATCH>(one, table, prefix, B, cbox::kTile, cbox::kTile, a, bx, by)) return;
+    if (!tile_of_block_xcd<BATCH>(one, table, prefix, B, kFwdTileW, kFwdTileH, a, bx, by)) return;
     BoxTile t;
-    t.x = (int)(bx * cbox::kTile) + (threadIdx.x & 15);
-    t.y = (int)(by * cbox::kTile) + (threadIdx.x >> 4);
+    t.x = (int)(bx * kFwdTileW) + fwd_tx(threadIdx.x);
+    t.y = (int)(by * kFwdTileH) + fwd_ty(threadIdx.x);
     const bool active = t.x < a.W && t.y < a.H;
     {
         const int64_t HW = a.H * a.W, idx = (int64_t)t.y * a.W + t.x;
@@ -784,13 +822,14 @@ __global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, cons
         }
     }
     tile_R_range(t.R, active, t.Rlo, t.Rhi);
-    t.x_lo = (int)(bx * cbox::kTile);
-    t.y_lo = (int)(by * cbox::kTile);
-    t.x_hi = (int)min((int64_t)t.x_lo + cbox::kTile - 1, a.W - 1);
-    t.y_hi = (int)min((int64_t)t.y_lo + cbox::kTile - 1, a.H - 1);
+    t.x_lo = (int)(bx * kFwdTileW);
+    t.y_lo = (int)(by * kFwdTileH);
+    t.x_hi = (int)min((int64_t)t.x_lo + kFwdTileW - 1, a.W - 1);
+    t.y_hi = (int)min((int64_t)t.y_lo + kFwdTileH - 1, a.H - 1);
     t.pad_left = (int)a.pad_left;
-    t.packed = cbox::pack_state(threadIdx.x & 15, threadIdx.x >> 4, t.R, t.Rlo, active);
-    if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi)) {
+    t.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    t.packed = cbox::pack_state(fwd_tx(threadIdx.x), fwd_ty(threadIdx.x), t.R, t.Rlo, active);
+    if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, kFwdRows)) {
         if (active) {
             if (a.off[6] == 1) t2n4_pixel<true>(a, t.x, t.y);
             else t2n4_pixel<false>(a, t.x, t.y);
@@ -801,13 +840,14 @@ __global__ __launch_bounds__(256, 2) void k_gather_t2n4_box(GatherArgs one, cons
 #pragma unroll
     for (int q = 0; q < 81; ++q) J[q] = 0;
     box_stage_async(a, s_box,
-                    cbox::box_of<cbox::order_at(0)>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left));
+                    cbox::box_of<cbox::order_at(0)>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left),
+                    t.wave);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     box_fwd_all<0>(a, s_box, active, t, J);
     // the pixel's position and phases are formed again here rather than held
     // through the loop
-    const int px = t.x_lo + (threadIdx.x & 15), py = t.y_lo + (threadIdx.x >> 4);
+    const int px = t.x_lo + fwd_tx(threadIdx.x), py = t.y_lo + fwd_ty(threadIdx.x);
     if (px >= a.W || py >= a.H) return;
     const int64_t HW = a.H * a.W, idx = (int64_t)py * a.W + px;
     float ph[4], sk[4];
@@ -912,6 +952,8 @@ GatherShape gather_shape(const Plan &p, const GatherArgs &a) {
             s.kind = 3;
         } else if (a.canon) {
             s.kind = 4;
+            s.tile_w = kFwdTileW;
+            s.tile_h = kFwdTileH;
         } else {
             s.kind = 2;
             const bool contig = a.off[6] == 1;
@@ -937,7 +979,7 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
     } else {
         grid = dim3((unsigned)((p.W + s.tile_w - 1) / s.tile_w), (unsigned)((p.H + s.tile_h - 1) / s.tile_h));
     }
-    dim3 block(256);
+    dim3 block(s.kind == 4 ? 64 * kFwdWaves : 256);
     const bool fp64 = p.arith == BSF_ARITH_FP64;
     if (s.kind == 0) {
         if (p.M == 4) {
