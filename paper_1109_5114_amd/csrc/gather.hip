@@ -614,6 +614,14 @@ __device__ __forceinline__ void shl_add(uint64_t &acc, uint64_t v, int sh) {
     }
 }
 
+// The lane number, computed anew at every use (not shared between uses).
+__device__ __forceinline__ int fresh_lane_id() {
+    int lo, id;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0" : "=v"(lo));
+    asm volatile("v_mbcnt_hi_u32_b32 %0, -1, %1" : "=v"(id) : "v"(lo));
+    return id;
+}
+
 // Tile of the forward cluster-box kernel: kFwdTileW columns by kFwdTileH rows
 // of pixels, one wavefront per 16 x 4 block of them, and the LDS box rows it
 // stages.
@@ -709,7 +717,7 @@ struct BoxTile {
     int Rlo[4], Rhi[4];
     int pad_left;
     int wave;              // wavefront of the pixel in its workgroup (uniform)
-    uint32_t packed;       // cbox::pack_state
+    const uint32_t *state; // cbox::pack_state of every thread of the tile, in LDS
 };
 
 
@@ -732,7 +740,11 @@ __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__res
         for (int q = 0; q < 81; ++q) J[q] = 0 - J[q];
     }
     if (active) {
-        int base = (I & 1) * kFwdElems + cbox::packed_base<C>(t.packed, t.x_lo, t.y_lo, t.Rlo, b);
+        // the state is read from LDS in every combination, at an index formed
+        // afresh from the lane number: neither the state, its decoded fields
+        // nor its address stay live across combinations
+        const uint32_t st = t.state[64 * t.wave + fresh_lane_id()];
+        int base = (I & 1) * kFwdElems + cbox::packed_base<C>(st, t.x_lo, t.y_lo, t.Rlo, b);
         int base_hi = base + 4 * cbox::kPitch;
         asm("" : "+v"(base), "+v"(base_hi));
         box_fwd_combo<C>(s_box + base, s_box + base_hi, J);
@@ -806,6 +818,7 @@ template <bool BATCH>
 __global__ __launch_bounds__(64 * kFwdWaves, 2) void k_gather_t2n4_box(
     GatherArgs one, const GatherArgs *__restrict__ table, const int64_t *__restrict__ prefix, int B) {
     __shared__ uint64_t s_box[2 * kFwdElems];
+    __shared__ uint32_t s_state[64 * kFwdWaves];
     GatherArgs a;
     int64_t bx, by;
     if (!tile_of_block_xcd<BATCH>(one, table, prefix, B, kFwdTileW, kFwdTileH, a, bx, by)) return;
@@ -828,7 +841,8 @@ __global__ __launch_bounds__(64 * kFwdWaves, 2) void k_gather_t2n4_box(
     t.y_hi = (int)min((int64_t)t.y_lo + kFwdTileH - 1, a.H - 1);
     t.pad_left = (int)a.pad_left;
     t.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    t.packed = cbox::pack_state(fwd_tx(threadIdx.x), fwd_ty(threadIdx.x), t.R, t.Rlo, active);
+    s_state[threadIdx.x] = cbox::pack_state(fwd_tx(threadIdx.x), fwd_ty(threadIdx.x), t.R, t.Rlo, active);
+    t.state = s_state;
     if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, kFwdRows)) {
         if (active) {
             if (a.off[6] == 1) t2n4_pixel<true>(a, t.x, t.y);
