@@ -636,9 +636,25 @@ static_assert(kFwdTileW % 16 == 0 && kFwdTileH % 4 == 0 && kFwdTileW + 64 * (kFw
 __device__ __forceinline__ int fwd_tx(int i) { return 16 * ((i >> 6) % (kFwdTileW / 16)) + (i & 15); }
 __device__ __forceinline__ int fwd_ty(int i) { return 4 * ((i >> 6) / (kFwdTileW / 16)) + ((i >> 4) & 3); }
 
-template <int C>
-__device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, const uint64_t *__restrict__ p_hi,
-                                              uint64_t J[81]) {
+// Patch row (Y + 2) of the lowest sub-tap a row tuple of combination C reads.
+__host__ __device__ constexpr int tuple_max_row(int C, int r0, int r1, int r2, int r3) {
+    using namespace cbox;
+    const int c0 = cl(C, 0), c1 = cl(C, 1), c2 = cl(C, 2), c3 = cl(C, 3);
+    int m = 0;
+    for (int i0 = 0; i0 < n_sub(c0, r0); ++i0)
+        for (int i1 = 0; i1 < n_sub(c1, r1); ++i1)
+            for (int i2 = 0; i2 < n_sub(c2, r2); ++i2)
+                for (int i3 = 0; i3 < n_sub(c3, r3); ++i3) {
+                    const int y = sub_q(c1, r1, i1) + sub_q(c2, r2, i2) - sub_q(c3, r3, i3) + 2;
+                    m = y > m ? y : m;
+                }
+    return m;
+}
+
+// Adds of the row tuples of combination C selected by PASS: 0 = those reading
+// patch rows 0-3 only with r0 == 0, 1 = the same with r0 > 0, 2 = the rest.
+template <int C, int PASS>
+__device__ __forceinline__ void box_fwd_pass(const uint64_t val[49], uint64_t J[81]) {
     using namespace cbox;
     constexpr int c0 = cl(C, 0), c1 = cl(C, 1), c2 = cl(C, 2), c3 = cl(C, 3);
 #pragma unroll
@@ -649,6 +665,9 @@ __device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, co
             for (int r2 = 0; r2 < n_rows(c2); ++r2)
 #pragma unroll
                 for (int r3 = 0; r3 < n_rows(c3); ++r3) {
+                    const bool upper = tuple_max_row(C, r0, r1, r2, r3) <= 3;
+                    const int pass = !upper ? 2 : r0 == 0 ? 0 : 1;
+                    if (pass != PASS) continue;
                     uint64_t v = 0;
 #pragma unroll
                     for (int i0 = 0; i0 < n_sub(c0, r0); ++i0)
@@ -657,11 +676,10 @@ __device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, co
 #pragma unroll
                             for (int i2 = 0; i2 < n_sub(c2, r2); ++i2)
 #pragma unroll
-                                for (int i3 = 0; i3 < n_sub(c3, r3); ++i3)
-                                {
-                                    const int e = sub_elem(sub_q(c0, r0, i0), sub_q(c1, r1, i1),
-                                                               sub_q(c2, r2, i2), sub_q(c3, r3, i3));
-                                    v += e < 4 * kPitch ? p[e] : p_hi[e - 4 * kPitch];
+                                for (int i3 = 0; i3 < n_sub(c3, r3); ++i3) {
+                                    const int q0 = sub_q(c0, r0, i0), q1 = sub_q(c1, r1, i1);
+                                    const int q2 = sub_q(c2, r2, i2), q3 = sub_q(c3, r3, i3);
+                                    v += val[(q0 + q2 + q3) + 7 * (q1 + q2 - q3 + 2)];
                                 }
                     const int sh = doubled(c0, r0) + doubled(c1, r1) + doubled(c2, r2) + doubled(c3, r3);
 #pragma unroll
@@ -676,6 +694,27 @@ __device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, co
                                                    out_o(c3, r3, j3))],
                                             v, sh);
                 }
+}
+
+// One combination: the 22 patch points of rows 0-3 are loaded together, the
+// tuples reading only those start, the 15 points of rows 4-6 are loaded
+// (kept below that first part by a scheduling barrier, so that not all 37
+// values are live at once), and the remaining tuples follow.
+template <int C>
+__device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, const uint64_t *__restrict__ p_hi,
+                                              uint64_t J[81]) {
+    using namespace cbox;
+    uint64_t val[49];
+#pragma unroll
+    for (int P = 0; P < 4 * 7; ++P)
+        if (kPatch.count[P] > 0) val[P] = p[point_elem(P)];
+    box_fwd_pass<C, 0>(val, J);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int P = 4 * 7; P < 49; ++P)
+        if (kPatch.count[P] > 0) val[P] = p_hi[point_elem(P) - 4 * kPitch];
+    box_fwd_pass<C, 1>(val, J);
+    box_fwd_pass<C, 2>(val, J);
 }
 
 // Start copying box b of the window into the LDS buffer dst (rows of kPitch
