@@ -10,8 +10,8 @@
 // anchor + (q0 + q2 + q3, q1 + q2 - q3), q in {0,1,2}^4: a 7 x 7 patch with
 // 37 distinct points, where anchor = x + sum_k base_k u_k.  Over a tile of
 // pixels the anchors move with the pixel and with 2 (R - R') along u_k, so a
-// combination of a tile (16 x 4 pixels in the gather, 16 x 16 in the adjoint)
-// reaches one small box of the running-sum window.  The gather stages that box in LDS and reads it at static offsets;
+// combination of a 16 x 16 tile reaches one small box of the running-sum
+// window.  The gather stages that box in LDS and reads it at static offsets;
 // the adjoint accumulates into it and adds it to the window once.
 //
 // The tensor of the 81 exact integer values J[o0][o1][o2][o3] (o = aa, ab,
@@ -128,7 +128,7 @@ __device__ __forceinline__ int pixel_base(int x, int y, const int R[4], const Bo
 }
 
 // The pixel's state through a combination loop, in one register: bits 0-9
-// hold tx + 64 ty (its position in the tile), then R_k - Rlo_k in five
+// hold tx + 64 ty (its position in the 16 x 16 tile), then R_k - Rlo_k in five
 // bits per direction (at most 20 whenever the boxes fit).  Inactive pixels
 // store zero differences.
 __device__ __forceinline__ uint32_t pack_state(int tx, int ty, const int R[4], const int Rlo[4], bool active) {

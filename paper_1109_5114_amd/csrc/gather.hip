@@ -593,9 +593,8 @@ __global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, cons
 
 // ----------------------------------------------------------------------------
 // Tied order-2 filter along (1,0), (0,1), (1,1), (1,-1) from LDS cluster boxes.
-// A tile of pixels (kFwdTileW x kFwdTileH below) visits the 81 cluster
-// combinations; for each it stages the combination's box of the window in LDS
-// with row-pair LDS-direct copies, and every
+// A 16 x 16 tile visits the 81 cluster combinations; for each it stages the
+// combination's box of the window in LDS with row-contiguous loads, and every
 // pixel reads its 37 distinct sub-patch points at static offsets from its
 // anchor and adds them into the 81 exact values J.  Combinations with an even
 // number of M clusters come first; J is then negated once, so the odd ones
@@ -624,24 +623,18 @@ __device__ __forceinline__ int fresh_lane_id() {
 }
 
 // Tile of the forward cluster-box kernel: kFwdTileW columns by kFwdTileH rows
-// of pixels, one wavefront per kFwdWaveW x (64 / kFwdWaveW) block of them, and
-// the LDS box rows it stages.
+// of pixels, one wavefront per 16 x 4 block of them, and the LDS box rows it
+// stages.
 constexpr int kFwdTileW = 16;
-constexpr int kFwdTileH = 4;
-constexpr int kFwdWaveW = 16;
-constexpr int kFwdWaveH = 64 / kFwdWaveW;
-constexpr int kFwdWaves = (kFwdTileW / kFwdWaveW) * (kFwdTileH / kFwdWaveH);
-constexpr int kFwdRows = 18;
+constexpr int kFwdTileH = 8;
+constexpr int kFwdWaves = (kFwdTileW / 16) * (kFwdTileH / 4);
+constexpr int kFwdRows = 32;
 constexpr int kFwdElems = cbox::kPitch * kFwdRows;
-static_assert(kFwdTileW % kFwdWaveW == 0 && kFwdTileH % kFwdWaveH == 0 && kFwdTileW + 64 * (kFwdTileH - 1) < 1024 &&
+static_assert(kFwdTileW % 16 == 0 && kFwdTileH % 4 == 0 && kFwdTileW + 64 * (kFwdTileH - 1) < 1024 &&
                   kFwdRows % 2 == 0, "tile shape");
 // Position of thread i's pixel in the tile.
-__device__ __forceinline__ int fwd_tx(int i) {
-    return kFwdWaveW * ((i >> 6) % (kFwdTileW / kFwdWaveW)) + (i & (kFwdWaveW - 1));
-}
-__device__ __forceinline__ int fwd_ty(int i) {
-    return kFwdWaveH * ((i >> 6) / (kFwdTileW / kFwdWaveW)) + ((i & 63) / kFwdWaveW);
-}
+__device__ __forceinline__ int fwd_tx(int i) { return 16 * ((i >> 6) % (kFwdTileW / 16)) + (i & 15); }
+__device__ __forceinline__ int fwd_ty(int i) { return 4 * ((i >> 6) / (kFwdTileW / 16)) + ((i >> 4) & 3); }
 
 // Patch row (Y + 2) of the lowest sub-tap a row tuple of combination C reads.
 __host__ __device__ constexpr int tuple_max_row(int C, int r0, int r1, int r2, int r3) {
