@@ -628,7 +628,7 @@ __device__ __forceinline__ int fresh_lane_id() {
 constexpr int kFwdTileW = 16;
 constexpr int kFwdTileH = 8;
 constexpr int kFwdWaves = (kFwdTileW / 16) * (kFwdTileH / 4);
-constexpr int kFwdRows = 32;
+constexpr int kFwdRows = 38;
 constexpr int kFwdElems = cbox::kPitch * kFwdRows;
 static_assert(kFwdTileW % 16 == 0 && kFwdTileH % 4 == 0 && kFwdTileW + 64 * (kFwdTileH - 1) < 1024 &&
                   kFwdRows % 2 == 0, "tile shape");
