@@ -80,8 +80,9 @@ typedef enum { BSF_ARITH_EXACT = 0, BSF_ARITH_FP64 = 1 } bsf_arith;
 #define BSF_MAX_FACTORS 16
 
 /* Device status bits (bsf_read_device_status). */
-#define BSF_FLAG_RANGE 1u
-#define BSF_FLAG_OVERFLOW 2u
+#define BSF_FLAG_RANGE 1u      /* a step NaN, below 1, above max_step, or non-integer in integer mode */
+#define BSF_FLAG_OVERFLOW 2u   /* a requested F leaves the tap combination without int64 headroom */
+#define BSF_FLAG_NONFINITE 4u  /* a NaN or infinite image sample or upstream gradient */
 
 /*
  * Filter configuration.
@@ -98,10 +99,13 @@ typedef enum { BSF_ARITH_EXACT = 0, BSF_ARITH_FP64 = 1 } bsf_arith;
  *              BSF_STEPS_REAL (continuous steps).
  *   max_step:  upper bound on every step (>= 1); it sizes the padding of the
  *              running-sum window.  Steps above it raise BSF_FLAG_RANGE.
- *   frac_bits: F for float images: >= 0 fixes it, -1 chooses on the device the
- *              largest F for which the tap combination cannot overflow, from the
- *              image's largest magnitude and the steps actually present.  Ignored
- *              for integer images (F = 0) and for BSF_ARITH_FP64.
+ *   frac_bits: F for float images: 0..62 fixes it, -1 chooses on the device the
+ *              largest F for which the tap combination cannot overflow,
+ *              F = 62 - ceil(log2 max|f|) - max_x ceil(log2 prod_j L_j(x)) with
+ *              L_j = 2 floor((s_j - 1)/2) + 3 (continuous) or s_j (integer steps):
+ *              it is not clamped, so images of tiny magnitude get F > 62 and
+ *              huge ones F < 0 (f_q = nearest-even(f 2^F) in both cases).
+ *              Ignored for integer images (F = 0) and for BSF_ARITH_FP64.
  *   arith:     BSF_ARITH_EXACT or BSF_ARITH_FP64.
  */
 typedef struct {

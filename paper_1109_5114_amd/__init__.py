@@ -19,7 +19,7 @@ OK, E_INVALID, E_RANGE, E_OVERFLOW, E_WORKSPACE, E_DEVICE, E_UNSUPPORTED = range
 U8, U16, F32 = 1, 2, 3
 STEPS_INT, STEPS_REAL = 0, 1
 ARITH_EXACT, ARITH_FP64 = 0, 1
-FLAG_RANGE, FLAG_OVERFLOW = 1, 2
+FLAG_RANGE, FLAG_OVERFLOW, FLAG_NONFINITE = 1, 2, 4
 MAX_DIRS = 8
 DIRS4 = ((1, 0), (0, 1), (1, 1), (1, -1))
 
@@ -396,6 +396,25 @@ def filter_batched(cfg: Config, imgs: Sequence[torch.Tensor], steps: Sequence[to
     return Batch(cfg, imgs, steps).run(use_graph)
 
 
+class DeviceFlagError(RuntimeError):
+    """A checked call found device status flags (FLAG_*) raised."""
+
+    def __init__(self, flags, what):
+        self.flags = flags
+        names = [n for n, b in (("RANGE", FLAG_RANGE), ("OVERFLOW", FLAG_OVERFLOW),
+                                ("NONFINITE", FLAG_NONFINITE)) if flags & b]
+        super().__init__("%s: device flags %s" % (what, "|".join(names) or hex(flags)))
+
+
+def check_flags(ws: Workspace, what: str = "bsf"):
+    """Synchronises, reads and clears the workspace's sticky flags, and raises
+    DeviceFlagError if any is set (a step out of range or NaN, a fixed-point
+    overflow, or a non-finite image sample or upstream gradient)."""
+    flags, _, _ = ws.status(clear=True)
+    if flags:
+        raise DeviceFlagError(flags, what)
+
+
 class _Filter(torch.autograd.Function):
     """out = space-variant box-spline filter of img with per-pixel steps.  The
     forward keeps d out / d steps (the filter is local in its steps); the
@@ -403,11 +422,18 @@ class _Filter(torch.autograd.Function):
     running sums for the image."""
 
     @staticmethod
-    def forward(ctx, img, steps, cfg):
+    def forward(ctx, img, steps, cfg, check):
         need_s = ctx.needs_input_grad[1]
         ds = torch.empty_like(steps) if need_s else None
-        out = filter_varying(cfg, img, steps, dsteps=ds)
+        H, W = img.shape
+        ws = _workspace(img.device, plan(cfg, H, W).workspace_bytes)
+        if check:
+            ws.status(clear=True)
+        out = filter_varying(cfg, img, steps, dsteps=ds, ws=ws)
+        if check:
+            check_flags(ws, "filter forward")
         ctx.cfg = cfg
+        ctx.check = check
         ctx.save_for_backward(steps, ds if need_s else steps)
         ctx.has_ds = need_s
         return out
@@ -415,16 +441,29 @@ class _Filter(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gout):
         steps, ds = ctx.saved_tensors
+        _, H, W = steps.shape
+        ws = _workspace(steps.device, backward_workspace_bytes(ctx.cfg, H, W))
+        if ctx.check:
+            ws.status(clear=True)
         gi, gs = filter_backward(ctx.cfg, steps, gout.contiguous(), dsteps=ds if ctx.has_ds else None,
-                                 want_img=ctx.needs_input_grad[0], want_steps=ctx.has_ds)
-        return gi, gs, None
+                                 want_img=ctx.needs_input_grad[0], want_steps=ctx.has_ds, ws=ws)
+        if ctx.check:
+            check_flags(ws, "filter backward")
+        return gi, gs, None, None
 
 
-def filter(img: torch.Tensor, steps: torch.Tensor, cfg: Config) -> torch.Tensor:
-    """Differentiable space-variant filter (continuous steps, float32 image)."""
+def filter(img: torch.Tensor, steps: torch.Tensor, cfg: Config, check: bool = False) -> torch.Tensor:
+    """Differentiable space-variant filter (continuous steps, float32 image).
+
+    Steps outside [1, max_step] (or NaN) are clamped on the device and raise
+    FLAG_RANGE; their step derivative is that of the clamped step.  A NaN or
+    infinite image sample or upstream gradient raises FLAG_NONFINITE (and makes
+    the image gradient NaN).  With check=True the forward and the backward
+    each read the flags (a synchronisation) and raise DeviceFlagError; without
+    it the caller reads them through Workspace.status()."""
     if cfg.mode != STEPS_REAL or img.dtype != torch.float32:
         raise ValueError("the differentiable filter takes a float32 image and continuous steps")
-    return _Filter.apply(img, steps, cfg)
+    return _Filter.apply(img, steps, cfg, bool(check))
 
 
 def version():

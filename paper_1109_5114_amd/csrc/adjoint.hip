@@ -12,9 +12,22 @@
 // omega_J = nearest(2^Fg g c_J / prod s), and everything after that is int64
 // modulo 2^64: the scatter of sum_J omega_J B_J into a window-sized array, and
 // the suffix sums S^T (the transposed, window-truncated running sums, last
-// direction first).  The result at every image pixel is bounded, so it comes
-// out exact; Fg is chosen from max |g| with 3 bits of headroom for the column
-// sums of the kernels.  The only error is the rounding of omega_J.
+// direction first).  Only the final value at each image pixel p has to fit in
+// 63 bits, and it is bounded by
+//     |V(p)| <= sum_x sum_J |round(omega_J(x))| K_J(p - x)
+//            <= 2 * 2^Fg max|g| * sum_x k_x(p - x)
+// (K_J >= 0 are the integer component kernels, k_x the pixel's normalised
+// kernel, and |round(w)| <= 2|w| for every w).  The column sum
+// sum_x k_x(p - x) has no fixed bound (pixels with long steps pointing at p
+// pile up), so it is bounded from the data before the scatter: every pixel's
+// kernel is at most kmax(x) = min(1, 1/S_(1), 1/(S_(1) S_(2))) (S_(1) >= S_(2)
+// the largest steps of two different directions: the factors of two
+// non-parallel directions meet at every lattice point at most once, and
+// further factors only spread mass) on the rectangle that holds its support,
+// and the sum of those rectangles, a 2-D prefix sum of a difference array, is
+// maximised over the image.  Fg = 61 - ceil(log2 max|g|) - ceil(log2 bound),
+// unclamped, so the weights keep their bits whatever the scale of g.  The
+// only error is the rounding of omega_J.
 #include "bsf_common.h"
 #include "cluster_box.h"
 
@@ -22,7 +35,7 @@ namespace bsf {
 namespace {
 
 constexpr int kTile = 16;
-constexpr int kColumnMarginBits = 3;
+constexpr int kKmaxBits = 24;  // fixed-point scale of the per-pixel kernel bounds
 
 __device__ __forceinline__ bool pixel_of_thread(int64_t H, int64_t W, int64_t &x, int64_t &y) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -39,39 +52,127 @@ __device__ __forceinline__ void atomic_add_i64(int64_t *p, int64_t v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
 }
 
+// A finite, nonzero upstream gradient scatters; zero scatters nothing and a
+// NaN or infinity is reported (and poisons grad_img) instead.
+__device__ __forceinline__ bool scatters(float g) { return g != 0.0f && fabsf(g) <= 3.402823466e38f; }
+
 __global__ void k_adj_begin(int32_t *status) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) status[ST_G_ABSMAX_BITS] = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        status[ST_G_ABSMAX_BITS] = 0;
+        status[ST_COLSUM_E] = -0x40000000;
+        status[ST_G_NONFINITE] = 0;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_adj_gmax(const float *__restrict__ g, int64_t H, int64_t W,
                                                   int32_t *status) {
     __shared__ unsigned s_b[4];
+    __shared__ int s_nf[4];
     unsigned b = 0;
+    int nf = 0;
     for (int64_t y = blockIdx.x; y < H; y += gridDim.x)
         for (int64_t x = threadIdx.x; x < W; x += blockDim.x) {
             const float v = fabsf(g[y * W + x]);
-            if (v == v) b = max(b, __float_as_uint(v));
+            if (v <= 3.402823466e38f) b = max(b, __float_as_uint(v));
+            else nf = 1;
         }
-    for (int d = 32; d >= 1; d >>= 1) b = max(b, (unsigned)__shfl_xor((int)b, d, 64));
-    if ((threadIdx.x & 63) == 0) s_b[threadIdx.x >> 6] = b;
+    for (int d = 32; d >= 1; d >>= 1) {
+        b = max(b, (unsigned)__shfl_xor((int)b, d, 64));
+        nf |= __shfl_xor(nf, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_b[threadIdx.x >> 6] = b;
+        s_nf[threadIdx.x >> 6] = nf;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = max(b, s_b[k]);
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            b = max(b, s_b[k]);
+            nf |= s_nf[k];
+        }
         atomicMax((unsigned *)&status[ST_G_ABSMAX_BITS], b);
+        if (nf) {
+            atomicOr((unsigned *)&status[ST_G_NONFINITE], 1u);
+            atomicOr((unsigned *)&status[ST_FLAGS], BSF_FLAG_NONFINITE);
+        }
+    }
+}
+
+// ceil(log2 v) for v >= 1, exact for every 64-bit value.
+__device__ __forceinline__ int ceil_log2_u64(uint64_t v) { return v <= 1 ? 0 : 64 - __builtin_clzll(v - 1); }
+
+// Column-sum bound, first part: each scattering pixel adds ceil(kmax 2^24) on
+// the rectangle of the image that holds its kernel's support, as the four
+// corners of a difference array D[(H + 1) x (W + 1)].  Along factor j the
+// kernel reaches |i| <= R_j + 1 lattice steps (R_j = floor((s_j - 1)/2)).
+__global__ __launch_bounds__(256) void k_adj_colsum_scatter(AdjointArgs a, uint64_t *__restrict__ D) {
+    int64_t x, y;
+    if (!pixel_of_thread(a.H, a.W, x, y)) return;
+    const int64_t HW = a.H * a.W, idx = y * a.W + x;
+    if (!scatters(a.gout[idx])) return;
+    float S[BSF_MAX_DIRS];
+    for (int k = 0; k < a.n_dirs; ++k) S[k] = 1.0f;
+    int64_t ex = 0, ey = 0;
+    for (int j = 0; j < a.M; ++j) {
+        const float s = clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
+        const int k = j / a.order;
+        S[k] = fmaxf(S[k], s);
+        const int64_t reach = (int64_t)floorf((s - 1.0f) * 0.5f) + 1;
+        ex += reach * a.adx[k];
+        ey += reach * a.ady[k];
+    }
+    float s1 = 1.0f, s2 = 1.0f;  // the two largest direction steps
+    for (int k = 0; k < a.n_dirs; ++k) {
+        if (S[k] > s1) {
+            s2 = s1;
+            s1 = S[k];
+        } else if (S[k] > s2) {
+            s2 = S[k];
+        }
+    }
+    const double kmax = 1.0 / ((double)s1 * (double)s2);
+    const uint64_t v = (uint64_t)ceil(__builtin_ldexp(kmax, kKmaxBits));
+    const int64_t W1 = a.W + 1;
+    const int64_t x0 = max(x - ex, (int64_t)0), x1 = min(x + ex, a.W - 1) + 1;
+    const int64_t y0 = max(y - ey, (int64_t)0), y1 = min(y + ey, a.H - 1) + 1;
+    atomicAdd((unsigned long long *)&D[y0 * W1 + x0], (unsigned long long)v);
+    atomicAdd((unsigned long long *)&D[y0 * W1 + x1], (unsigned long long)(0 - v));
+    atomicAdd((unsigned long long *)&D[y1 * W1 + x0], (unsigned long long)(0 - v));
+    atomicAdd((unsigned long long *)&D[y1 * W1 + x1], (unsigned long long)v);
+}
+
+// Column-sum bound, last part: after the 2-D prefix sum D(p) bounds
+// 2^24 sum_x k_x(p - x); its largest ceil(log2) over the image, minus 24.
+__global__ __launch_bounds__(256) void k_adj_colsum_max(const uint64_t *__restrict__ D, int64_t H, int64_t W,
+                                                        int32_t *status) {
+    __shared__ int s_e[4];
+    int e = -0x40000000;
+    const int64_t W1 = W + 1;
+    for (int64_t y = blockIdx.x; y < H; y += gridDim.x)
+        for (int64_t x = threadIdx.x; x < W; x += blockDim.x) {
+            const uint64_t v = D[y * W1 + x];
+            if (v) e = max(e, ceil_log2_u64(v) - kKmaxBits);
+        }
+    for (int d = 32; d >= 1; d >>= 1) e = max(e, __shfl_xor(e, d, 64));
+    if ((threadIdx.x & 63) == 0) s_e[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) e = max(e, s_e[k]);
+        atomicMax(&status[ST_COLSUM_E], e);
     }
 }
 
 __global__ void k_adj_choose_Fg(int32_t *status) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const float gmax = __uint_as_float((unsigned)status[ST_G_ABSMAX_BITS]);
+    const int eb = status[ST_COLSUM_E];
     int Fg = 0;
-    if (gmax > 0.0f) {
+    if (gmax > 0.0f && eb > -0x40000000) {
         int e;
         const double m = __builtin_frexp((double)gmax, &e);
         const int eg = (m == 0.5) ? e - 1 : e;  // |g| <= 2^eg
-        Fg = 62 - eg - kColumnMarginBits;
-        if (Fg > 62) Fg = 62;
-        if (Fg < 0) Fg = 0;
+        // |V| <= 2 * 2^Fg * 2^eg * 2^eb <= 2^62; every |omega| <= 2^Fg 2^eg 2^eb too
+        Fg = 61 - eg - eb;
     }
     status[ST_FG] = Fg;
 }
@@ -103,7 +204,7 @@ __device__ __forceinline__ int64_t expand3(int p, const int64_t v[3]) {
 __device__ __forceinline__ void adj_t2n4_pixel(const AdjointArgs &a, int64_t x, int64_t y) {
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const float g = a.gout[idx];
-    if (!(g != 0.0f)) return;  // zero (or NaN) upstream gradient scatters nothing
+    if (!scatters(g)) return;
     const int Fg = a.status[ST_FG];
     int64_t o[4][9];
     double w[4][3];
@@ -286,7 +387,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_scatter_t2n4_box(AdjointArgs a) 
     const bool inside = t.x < a.W && t.y < a.H;
     const int64_t HW = a.H * a.W, idx = (int64_t)t.y * a.W + t.x;
     const float g = inside ? a.gout[idx] : 0.0f;
-    const bool active = inside && (g != 0.0f);  // zero (or NaN) upstream gradient scatters nothing
+    const bool active = inside && scatters(g);
     float ph[4];
     double den = 1.0;
 #pragma unroll
@@ -376,7 +477,7 @@ __global__ __launch_bounds__(256) void k_adj_scatter_generic(AdjointArgs a) {
     const int M = a.M;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const float g = a.gout[idx];
-    if (!(g != 0.0f)) return;
+    if (!scatters(g)) return;
     const int Fg = a.status[ST_FG];
     int64_t pos[BSF_MAX_FACTORS][4];
     double ph[BSF_MAX_FACTORS];
@@ -420,9 +521,12 @@ __global__ __launch_bounds__(256) void k_adj_finish(const int64_t *__restrict__ 
     if (x >= W) return;
     const int64_t HW = H * W;
     const int Fg = status[ST_FG];
+    const bool poisoned = status[ST_G_NONFINITE] != 0;
     for (int64_t y = blockIdx.y; y < H; y += gridDim.y) {
         const int64_t idx = y * W + x;
-        if (grad_img) grad_img[idx] = (float)__builtin_ldexp((double)Ghat[(y + pad_top) * Wp + (x + pad_left)], -Fg);
+        if (grad_img)
+            grad_img[idx] = poisoned ? __builtin_nanf("")
+                                     : (float)__builtin_ldexp((double)Ghat[(y + pad_top) * Wp + (x + pad_left)], -Fg);
         if (grad_steps) {
             const float g = gout[idx];
             for (int q = 0; q < planes; ++q) grad_steps[q * HW + idx] = g * dsteps[q * HW + idx];
@@ -432,21 +536,35 @@ __global__ __launch_bounds__(256) void k_adj_finish(const int64_t *__restrict__ 
 
 }  // namespace
 
-bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *status, hipStream_t st) {
+int64_t fill_blocks(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return b < 1 ? 1 : b > 65536 ? 65536 : b;
+}
+
+bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *status, void *aux, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_begin, dim3(1), dim3(64), 0, st, status);
     BSF_HIP_CHECK(hipGetLastError());
     int64_t blocks = p.H < 2048 ? p.H : 2048;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_adj_gmax, dim3((unsigned)blocks), dim3(256), 0, st, a.gout, p.H, p.W, status);
     BSF_HIP_CHECK(hipGetLastError());
+    dim3 grid((unsigned)((p.W + kTile - 1) / kTile), (unsigned)((p.H + kTile - 1) / kTile));
+    // the column-sum bound, built in the window's memory before the scatter
+    const int64_t nd = (p.H + 1) * (p.W + 1);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)fill_blocks(nd)), dim3(256), 0, st, a.Ghat, nd);
+    BSF_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_adj_colsum_scatter, grid, dim3(256), 0, st, a, reinterpret_cast<uint64_t *>(a.Ghat));
+    BSF_HIP_CHECK(hipGetLastError());
+    bsf_status r = run_prefix2d(a.Ghat, p.H + 1, p.W + 1, aux, st);
+    if (r != BSF_OK) return r;
+    hipLaunchKernelGGL(k_adj_colsum_max, dim3((unsigned)blocks), dim3(256), 0, st,
+                       reinterpret_cast<const uint64_t *>(a.Ghat), p.H, p.W, status);
+    BSF_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_adj_choose_Fg, dim3(1), dim3(64), 0, st, status);
     BSF_HIP_CHECK(hipGetLastError());
     const int64_t n = p.Hp * p.Wp;
-    int64_t fb = (n + 255) / 256;
-    if (fb > 65536) fb = 65536;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)fb), dim3(256), 0, st, a.Ghat, n);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)fill_blocks(n)), dim3(256), 0, st, a.Ghat, n);
     BSF_HIP_CHECK(hipGetLastError());
-    dim3 grid((unsigned)((p.W + kTile - 1) / kTile), (unsigned)((p.H + kTile - 1) / kTile));
     if (p.n_dirs == 4 && p.order == 2 && p.tied && a.canon)
         hipLaunchKernelGGL(k_adj_scatter_t2n4_box, dim3((unsigned)xcd_grid((int64_t)grid.x * grid.y)), dim3(256), 0,
                            st, a);

@@ -367,7 +367,11 @@ bsf_status bsf_filter_backward(const bsf_config *cfg, int64_t H, int64_t W, cons
         memcpy(a.plane, ga.plane, sizeof(a.plane));
         a.canon = ga.canon;
         memcpy(a.canon_plane, ga.canon_plane, sizeof(a.canon_plane));
-        r = run_adjoint_scatter(p, a, L.status, st);
+        for (int k = 0; k < p.n_dirs; ++k) {
+            a.adx[k] = p.dx[k] < 0 ? -p.dx[k] : p.dx[k];
+            a.ady[k] = p.dy[k] < 0 ? -p.dy[k] : p.dy[k];
+        }
+        r = run_adjoint_scatter(p, a, L.status, L.aux, st);
         if (r != BSF_OK) return r;
         r = run_preintegrate_transpose(p, L.G, L.aux, st);
         if (r != BSF_OK) return r;

@@ -113,6 +113,9 @@ bsf_status run_preintegrate(const Plan &p, const Src &src, void *G, void *aux, c
                             hipStream_t st);
 // Reverse (transposed) running sums on the window, last direction first.
 bsf_status run_preintegrate_transpose(const Plan &p, void *G, void *aux, hipStream_t st);
+// Inclusive 2-D prefix sum, in place, of a dense int64 [rows][cols] array
+// (rows <= Hp and cols <= Wp of a plan whose scan_aux_bytes sized aux).
+bsf_status run_prefix2d(int64_t *D, int64_t rows, int64_t cols, void *aux, hipStream_t st);
 
 // Per-pixel taps (gather.hip).
 struct GatherArgs {
@@ -165,8 +168,10 @@ bsf_status run_bound(const Plan &p, const Src &src, const float *steps, int32_t 
 // Adjoint (adjoint.hip).  Status words of the backward pass live in the
 // workspace's status block after the forward ones.
 enum AdjStatusWord : int {
-    ST_G_ABSMAX_BITS = 16,  // scratch: float bits of max |gout|
+    ST_G_ABSMAX_BITS = 16,  // scratch: float bits of max |gout| over the finite values
     ST_FG = 17,             // fixed-point bits of the scattered adjoint weights
+    ST_COLSUM_E = 18,       // scratch: ceil(log2) of the bound on sum_x k_x(p - x), max over p
+    ST_G_NONFINITE = 19,    // this backward call saw a NaN or infinite upstream gradient
 };
 
 struct AdjointArgs {
@@ -182,8 +187,10 @@ struct AdjointArgs {
     int32_t plane[BSF_MAX_FACTORS];
     int32_t canon;            // as in GatherArgs
     int32_t canon_plane[4];
+    int32_t adx[BSF_MAX_DIRS], ady[BSF_MAX_DIRS];  // |dx|, |dy| of each direction (config order)
 };
-bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *status, hipStream_t st);
+// aux: scan carries (at least scan_aux_bytes of the plan).
+bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *status, void *aux, hipStream_t st);
 bsf_status run_adjoint_finish(const Plan &p, const int64_t *Ghat, const int32_t *status, float *grad_img,
                               const float *gout, const float *dsteps, float *grad_steps, hipStream_t st);
 

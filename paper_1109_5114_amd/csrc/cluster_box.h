@@ -90,7 +90,7 @@ __host__ __device__ constexpr PatchTable make_patch_table() {
 constexpr PatchTable kPatch = make_patch_table();
 __host__ __device__ constexpr int point_elem(int P) { return (P % 7) + kPitch * (P / 7); }
 
-__device__ __forceinline__ int base_of(int c, int R) { return c == 0 ? 2 * R : c == 1 ? -2 : -2 * R - 4; }
+__host__ __device__ __forceinline__ int base_of(int c, int R) { return c == 0 ? 2 * R : c == 1 ? -2 : -2 * R - 4; }
 
 // Box of combination C for a tile whose active pixels span [x_lo, x_hi] x
 // [y_lo, y_hi] with R_k in [Rlo_k, Rhi_k]: image coordinates (ox, oy) of box
@@ -103,7 +103,7 @@ struct Box {
 };
 
 template <int C>
-__device__ __forceinline__ Box box_of(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4], const int Rhi[4],
+__host__ __device__ __forceinline__ Box box_of(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4], const int Rhi[4],
                                       int pad_left) {
     int bmin[4], bmax[4];
 #pragma unroll
@@ -120,18 +120,21 @@ __device__ __forceinline__ Box box_of(int x_lo, int x_hi, int y_lo, int y_hi, co
 
 // LDS element of the pixel's patch row Y = -2, column X = 0.
 template <int C>
-__device__ __forceinline__ int pixel_base(int x, int y, const int R[4], const Box &b) {
+__host__ __device__ __forceinline__ int pixel_base(int x, int y, const int R[4], const Box &b) {
     const int b0 = base_of(cl(C, 0), R[0]), b1 = base_of(cl(C, 1), R[1]);
     const int b2 = base_of(cl(C, 2), R[2]), b3 = base_of(cl(C, 3), R[3]);
     const int ax = x + b0 + b2 + b3, ay = y + b1 + b2 - b3;
     return (ay - 2 - b.oy) * kPitch + (ax - b.ox);
 }
 
+// (These index functions are also compiled for the host, where a test walks
+// them over random tiles, step ranges and window geometries.)
+//
 // The pixel's state through a combination loop, in one register: bits 0-9
 // hold tx + 64 ty (its position in the 16 x 16 tile), then R_k - Rlo_k in five
 // bits per direction (at most 20 whenever the boxes fit).  Inactive pixels
 // store zero differences.
-__device__ __forceinline__ uint32_t pack_state(int tx, int ty, const int R[4], const int Rlo[4], bool active) {
+__host__ __device__ __forceinline__ uint32_t pack_state(int tx, int ty, const int R[4], const int Rlo[4], bool active) {
     uint32_t st = (uint32_t)(tx + kPitch * ty);
 #pragma unroll
     for (int k = 0; k < 4; ++k) st |= (uint32_t)(active ? R[k] - Rlo[k] : 0) << (10 + 5 * k);
@@ -143,7 +146,7 @@ __device__ __forceinline__ uint32_t pack_state(int tx, int ty, const int R[4], c
 // and b_k = 2 R_k (T), -2 (M), -2 R_k - 4 (B); the tile-uniform part is
 // formed once per combination.
 template <int C>
-__device__ __forceinline__ int packed_base(uint32_t st, int x_lo, int y_lo, const int Rlo[4], const Box &b) {
+__host__ __device__ __forceinline__ int packed_base(uint32_t st, int x_lo, int y_lo, const int Rlo[4], const Box &b) {
     static_assert(kPitch == 64, "coefficients assume a 64-element pitch");
     constexpr int coef[4] = {1, 64, 65, -63};
     int v = (int)(st & 1023u);
@@ -167,7 +170,7 @@ __device__ __forceinline__ int packed_base(uint32_t st, int x_lo, int y_lo, cons
 
 // Largest box over the combinations (all clusters T or B, one column of
 // alignment) fits an LDS box of the given number of rows.
-__device__ __forceinline__ bool boxes_fit(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4],
+__host__ __device__ __forceinline__ bool boxes_fit(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4],
                                           const int Rhi[4], int rows = kRows) {
     const int d0 = Rhi[0] - Rlo[0], d1 = Rhi[1] - Rlo[1], d2 = Rhi[2] - Rlo[2], d3 = Rhi[3] - Rlo[3];
     const int w = (x_hi - x_lo) + 8 + 2 * (d0 + d2 + d3);

@@ -137,7 +137,7 @@ template <bool BATCH>
 __global__ __launch_bounds__(256) void k_bound(BoundJob one, const BoundJob *__restrict__ jobs,
                                                const int64_t *__restrict__ prefix, int B, int planes, int per_plane,
                                                int mode, float max_step) {
-    __shared__ int s_ep[4], s_bad[4];
+    __shared__ int s_ep[4], s_bad[4], s_nf[4];
     __shared__ unsigned s_fb[4];
     BoundJob job;
     int64_t first, stride;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_bound(BoundJob one, const BoundJob *__r
     }
     int ep_max = 0;
     unsigned fbits = 0;
-    int bad = 0;
+    int bad = 0, nonfinite = 0;
     const int64_t H = job.H, W = job.W, HW = H * W;
     for (int64_t y = first; y < H; y += stride) {
         for (int64_t x = threadIdx.x; x < W; x += blockDim.x) {
@@ -178,7 +178,8 @@ __global__ __launch_bounds__(256) void k_bound(BoundJob one, const BoundJob *__r
             ep_max = max(ep_max, ceil_log2(prod * (1.0 + 0x1p-40)));
             if (job.img) {
                 const float f = fabsf(job.img[y * job.pitch + x]);
-                if (f == f) fbits = max(fbits, __float_as_uint(f));
+                if (f <= 3.402823466e38f) fbits = max(fbits, __float_as_uint(f));
+                else nonfinite = 1;  // NaN or infinity
             }
         }
     }
@@ -186,12 +187,14 @@ __global__ __launch_bounds__(256) void k_bound(BoundJob one, const BoundJob *__r
         ep_max = max(ep_max, __shfl_xor(ep_max, d, 64));
         fbits = max(fbits, (unsigned)__shfl_xor((int)fbits, d, 64));
         bad |= __shfl_xor(bad, d, 64);
+        nonfinite |= __shfl_xor(nonfinite, d, 64);
     }
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         s_ep[w] = ep_max;
         s_fb[w] = fbits;
         s_bad[w] = bad;
+        s_nf[w] = nonfinite;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -199,10 +202,12 @@ __global__ __launch_bounds__(256) void k_bound(BoundJob one, const BoundJob *__r
             ep_max = max(ep_max, s_ep[k]);
             fbits = max(fbits, s_fb[k]);
             bad |= s_bad[k];
+            nonfinite |= s_nf[k];
         }
         atomicMax(&job.status[ST_EP_MAX], ep_max);
         if (job.img) atomicMax((unsigned *)&job.status[ST_FABS_BITS], fbits);
         if (bad) atomicOr((unsigned *)&job.status[ST_FLAGS], BSF_FLAG_RANGE);
+        if (nonfinite) atomicOr((unsigned *)&job.status[ST_FLAGS], BSF_FLAG_NONFINITE);
     }
 }
 
@@ -233,9 +238,9 @@ __global__ void k_choose_F(BoundJob one, const BoundJob *__restrict__ jobs, int 
     } else if (status[ST_F_REQUEST] >= 0) {
         F = status[ST_F_REQUEST];
     } else {
+        // not clamped: a tiny image keeps its significant bits (F > 62), a
+        // huge one is quantised more coarsely (F < 0) instead of overflowing
         F = 62 - (zero ? 0 : ef) - eP;
-        if (F > 62) F = 62;
-        if (F < 0) F = 0;
     }
     // |f_q| <= 2^(ef + F) (+1/2 from rounding) and |J| <= |f_q| * prod <= 2^(ef + F + eP)
     if (arith == BSF_ARITH_EXACT && !zero && ef + F + eP > 62)

@@ -357,7 +357,8 @@ LineGeom line_geom(int dx, int dy, int64_t Hp, int64_t Wp, int tl) {
 }
 
 size_t scan_aux_bytes(const Plan &p) {
-    size_t m = 0;
+    // the column pass of run_prefix2d over at most the window's size
+    size_t m = line_aux_bytes(0, 1, p.Hp, p.Wp, 1);
     for (int k = 0; k < p.n_dirs; ++k) {
         // both the forward pass (dx, dy) and the transposed one (-dx, -dy)
         if (p.dy[k] == 0) continue;
@@ -389,6 +390,14 @@ bsf_status run_preintegrate_transpose(const Plan &p, void *G, void *aux, hipStre
         if (r != BSF_OK) return r;
     }
     return BSF_OK;
+}
+
+bsf_status run_prefix2d(int64_t *D, int64_t rows, int64_t cols, void *aux, hipStream_t st) {
+    Src s{};
+    s.kind = SRC_WINDOW;
+    bsf_status r = pass_single(BSF_ARITH_EXACT, 1, 1, 0, rows, cols, s, D, aux, nullptr, st);
+    if (r != BSF_OK) return r;
+    return pass_single(BSF_ARITH_EXACT, 1, 0, 1, rows, cols, s, D, aux, nullptr, st);
 }
 
 bsf_status run_pass_batch(int arith, int order, int src_kind, int dx, int dy, const ScanJob *jobs,

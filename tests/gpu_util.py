@@ -22,8 +22,47 @@ def cfg_of(d, **kw):
     return bsf.Config(**args)
 
 
+def _ceil_log2(v):
+    """ceil(log2 v) of float64 values >= 1, from the binary exponent."""
+    m, e = np.frexp(np.asarray(v, dtype=np.float64))
+    return np.where(m == 0.5, e - 1, e)
+
+
+def expected_F(cfg, img, steps):
+    """The fixed-point bits F the library must choose for this input, computed
+    on the host from the rule it documents:
+        F = 62 - ceil(log2 max|f|) - max_x ceil(log2 prod_j L_j(x)),
+    L_j = 2 floor((s_j - 1)/2) + 3 for continuous steps and s_j for integer
+    steps (steps clamped to [1, max_step] in float32), the product taken in
+    float64 and raised by 2^-40 so that it stays an upper bound; integer
+    images use F = 0 and a fixed frac_bits is used as given.  Tests assert that
+    the device chose exactly this F, so a tolerance sized from it does not
+    follow a regression of the device's choice."""
+    if img.dtype != np.float32:
+        return 0
+    if cfg.frac_bits >= 0:
+        return int(cfg.frac_bits)
+    planes = steps.shape[0]
+    per_plane = cfg.order if cfg.tied else 1
+    prod = np.ones(steps.shape[1:], dtype=np.float64)
+    for q in range(planes):
+        sc = np.fmin(np.fmax(steps[q].astype(np.float32), np.float32(1.0)), np.float32(cfg.max_step))
+        if cfg.mode == bsf.STEPS_INT:
+            ln = np.rint(sc).astype(np.float64)
+        else:
+            ln = (np.float32(2.0) * np.floor((sc - np.float32(1.0)) * np.float32(0.5)) + np.float32(3.0))
+            ln = ln.astype(np.float64)
+        for _ in range(per_plane):
+            prod = prod * ln
+    eP = int(_ceil_log2(prod * (1.0 + 2.0 ** -40)).max()) if prod.size else 0
+    fmax = float(np.abs(img[np.isfinite(img)]).max()) if img.size else 0.0
+    ef = 0 if fmax == 0.0 else int(_ceil_log2(fmax))
+    return 62 - ef - eP
+
+
 def run_forward(cfg, img, steps, want_num=False, want_den=False, ws=None):
-    """Returns (out, num, den, flags, F) as numpy."""
+    """Returns (out, num, den, flags, F) as numpy.  F is the host's expected
+    F (expected_F), after checking that the device used exactly that."""
     dev = torch.device("cuda:0")
     ti = torch.from_numpy(np.ascontiguousarray(img)).to(dev)
     ts = torch.from_numpy(np.ascontiguousarray(steps, dtype=np.float32)).to(dev)
@@ -32,7 +71,9 @@ def run_forward(cfg, img, steps, want_num=False, want_den=False, ws=None):
     res = bsf.filter_varying(cfg, ti, ts, want_num=want_num, want_den=want_den, ws=ws)
     if not isinstance(res, tuple):
         res = (res,)
-    flags, F, _ = ws.status()
+    flags, F_dev, _ = ws.status()
+    F = expected_F(cfg, np.asarray(img), np.asarray(steps, dtype=np.float32))
+    assert F_dev == F, "device chose F = %d, the documented rule gives %d" % (F_dev, F)
     out = res[0].cpu().numpy()
     num = res[1].cpu().numpy() if want_num else None
     den = res[-1].cpu().numpy() if want_den else None

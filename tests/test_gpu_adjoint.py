@@ -189,3 +189,148 @@ def test_full_size_image_gradient_crops():
     pix = np.concatenate([rng.integers(0, H * W, 40), [0, W - 1, H * W - 1]])
     _, rgs = O.grad_real(img, DIRS4, 2, True, steps, g, pix=pix, want_img=False)
     assert_grad_close(gs.reshape(4, -1)[:, pix].T, rgs, what="grad_steps sampled")
+
+
+# ----------------------------------------------------------------------------- fixed-point headroom
+
+def backward_only(cfg, steps, g, ws=None):
+    dev = torch.device("cuda:0")
+    ts, tg = torch.from_numpy(steps).to(dev), torch.from_numpy(g).to(dev)
+    H, W = g.shape
+    ws = ws or bsf.Workspace(bsf.backward_workspace_bytes(cfg, H, W), dev)
+    gi, _ = bsf.filter_backward(cfg, ts, tg, want_steps=False, ws=ws)
+    return gi.cpu().numpy(), ws
+
+
+def test_small_upstream_gradient_keeps_its_bits():
+    """The image gradient is linear in g and its fixed point follows the scale
+    of g: a mean-style upstream gradient 2^-24 g gives exactly 2^-24 times the
+    gradient of g (steps up to 48, as in the 4096^2 workload), and both match
+    the FP64 oracle."""
+    note("adjoint small g")
+    d = WL.workload2(160, 176)
+    img, steps = d["img"], d["steps"]
+    g = np.random.default_rng(61).standard_normal(img.shape).astype(np.float32)
+    gs = (g * np.float32(2.0 ** -24)).astype(np.float32)
+    cfg = bsf.Config(order=2, max_step=d["max_step"])
+    gi, _ = backward_only(cfg, steps, g)
+    gi_s, _ = backward_only(cfg, steps, gs)
+    np.testing.assert_array_equal(gi_s, (gi * np.float32(2.0 ** -24)).astype(np.float32))
+    rgi, _ = O.grad_real(img, DIRS4, 2, True, steps, gs, want_steps=False)
+    assert_grad_close(gi_s, rgi, what="grad_img, g scaled by 2^-24")
+
+
+def tri(s, d):
+    """Order-2 kernel of one direction at odd integer step s, offset d: the
+    self-convolution of the length-s box, (s - |d|) / s^2 for |d| < s."""
+    d = np.abs(d)
+    return np.where(d < s, (s - d) / (s * s), 0.0)
+
+
+def test_triangle_closed_form_is_the_oracle_factor():
+    """Pins tri() to the oracle's factor weights: the convolution of two
+    normalised boxes of step s."""
+    for s in (1, 3, 7, 21, 101):
+        i, w = O.weights_real(float(s))
+        phi2 = np.convolve(w / s, w / s)
+        dd = np.arange(-2 * i[-1], 2 * i[-1] + 1)
+        np.testing.assert_allclose(phi2, tri(s, dd), rtol=0, atol=1e-15)
+
+
+@pytest.mark.timeout(300)
+def test_column_sum_headroom_adversarial():
+    """Every pixel's axis steps just reach the centre column and row
+    (s = 2 |x - c| + 1 along (1,0), 2 |y - c| + 1 along (0,1), diagonal steps 1),
+    so their kernels pile up on the centre: with g = 1 the image gradient there
+    is the column sum sum_x k_x(c - x) ~ 22, more than the 16 a fixed 3-bit
+    margin allows.  The kernels are separable products of triangles, so the
+    whole gradient is the outer product of two 1-D sums, compared at every
+    pixel."""
+    n, c = 2049, 1024
+    S = float(2 * c + 1)
+    note("adjoint adversarial column sums", n)
+    off = np.abs(np.arange(n) - c)
+    s_ax = (2 * off + 1).astype(np.float32)
+    steps = np.ones((4, n, n), dtype=np.float32)
+    steps[0] = s_ax[None, :]
+    steps[1] = s_ax[:, None]
+    g = np.ones((n, n), dtype=np.float32)
+    # A[p] = sum_x tri(s(x), p - x): the same for rows and columns
+    A = np.zeros(n)
+    for x in range(n):
+        s = int(s_ax[x])
+        lo, hi = max(0, x - s + 1), min(n, x + s)
+        A[lo:hi] += tri(s, np.arange(lo, hi) - x)
+    ref = np.outer(A, A)
+    assert ref[c, c] > 16.0
+    cfg = bsf.Config(order=2, max_step=S)
+    gi, ws = backward_only(cfg, steps, g)
+    flags, _, _ = ws.status()
+    assert flags == 0
+    assert_grad_close(gi, ref, rel_norm=1e-6, rel_max=1e-6, what="adversarial grad_img")
+
+
+def test_nonfinite_upstream_gradient():
+    """A NaN or infinite upstream gradient raises FLAG_NONFINITE and makes the
+    image gradient NaN; the next call with a finite gradient is clean again."""
+    note("adjoint non-finite g")
+    img, steps, g = case((24, 28), 4, 1.0, 7.0, 63)
+    cfg = bsf.Config(order=2, max_step=7.0)
+    bad = g.copy()
+    bad[5, 6] = np.nan
+    bad[9, 2] = np.inf
+    gi, ws = backward_only(cfg, steps, bad)
+    flags, _, _ = ws.status(clear=True)
+    assert flags & bsf.FLAG_NONFINITE
+    assert np.isnan(gi).all()
+    gi2, _ = backward_only(cfg, steps, g, ws=ws)
+    flags, _, _ = ws.status()
+    assert flags == 0 and np.isfinite(gi2).all()
+    rgi, _ = O.grad_real(img, DIRS4, 2, True, steps, g, want_steps=False)
+    assert_grad_close(gi2, rgi, what="grad_img after a NaN call")
+
+
+def test_checked_filter_raises_on_device_flags():
+    note("checked filter")
+    img, steps, g = case((20, 24), 4, 1.0, 6.0, 65)
+    cfg = bsf.Config(order=2, max_step=6.0)
+    dev = torch.device("cuda:0")
+    steps[1, 3, 3] = np.nan
+    ti = torch.from_numpy(img).to(dev).requires_grad_(True)
+    ts = torch.from_numpy(steps).to(dev)
+    with pytest.raises(bsf.DeviceFlagError):
+        bsf.filter(ti, ts, cfg, check=True)
+    steps[1, 3, 3] = 2.0
+    out = bsf.filter(ti, torch.from_numpy(steps).to(dev), cfg, check=True)
+    bad = torch.from_numpy(g).to(dev)
+    bad[0, 0] = float("inf")
+    with pytest.raises(bsf.DeviceFlagError):
+        out.backward(bad)
+
+
+@pytest.mark.timeout(600)
+def test_differentiation_workload_every_image():
+    """All 16 images of the differentiation workload (1024^2, steps in
+    [1.5, 20], standard-normal upstream gradient), each through the forward
+    and the adjoint as the benchmark runs them: the output, the step gradient
+    and the image gradient on the 64 x 64 crop of every image against the FP64
+    oracle."""
+    d = WL.workload5()
+    y0, y1, x0, x1 = d["fd_crop"]
+    cfg = bsf.Config(order=2, max_step=20.0)
+    m = 74   # reach of a step-20 order-2 kernel: 2 (R + 2) 3 + 8
+    for b in range(len(d["imgs"])):
+        note("workload 5 image", b)
+        img, steps, g = d["imgs"][b], d["steps"][b], d["gout"][b]
+        out, gi, gs, _ = gpu_grads(cfg, img, steps, g)
+        H, W = img.shape
+        ys, xs = np.mgrid[y0:y1, x0:x1]
+        pix = (ys * W + xs).reshape(-1)
+        ref = O.filter(img, DIRS4, 2, True, O.REAL, steps, pix=pix)
+        np.testing.assert_allclose(out.reshape(-1)[pix], ref, rtol=2e-7, atol=2e-8)
+        _, rgs = O.grad_real(img, DIRS4, 2, True, steps, g, pix=pix, want_img=False)
+        assert_grad_close(gs.reshape(4, -1)[:, pix].T, rgs, what="grad_steps image %d" % b)
+        rgi, _ = O.grad_real(img, DIRS4, 2, True, steps, g,
+                             window=(max(0, x0 - m), min(W, x1 + m), max(0, y0 - m), min(H, y1 + m)),
+                             want_steps=False)
+        assert_grad_close(gi[y0:y1, x0:x1], rgi[y0:y1, x0:x1], what="grad_img image %d" % b)

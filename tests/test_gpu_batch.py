@@ -10,7 +10,7 @@ import torch
 import oracle as O
 import paper_1109_5114_amd as bsf
 import workloads as WL
-from tests.gpu_util import assert_close, cfg_of, note
+from tests.gpu_util import assert_close, cfg_of, expected_F, note
 
 pytestmark = pytest.mark.gpu
 
@@ -107,7 +107,7 @@ def test_batch_status_collects_image_flags():
     batch.run(use_graph=False)
     flags, F, bound = batch.ws.status(clear=True)
     assert flags & bsf.FLAG_RANGE
-    assert 0 < F <= 62
+    assert F == min(expected_F(cfg, im, st) for im, st in zip(imgs, steps))
     flags, _, _ = batch.ws.status()
     assert flags == 0
 
@@ -123,6 +123,7 @@ def test_isotropic_batch_matches_oracle():
     batch = bsf.Batch(cfg, to_dev(imgs), to_dev(steps))
     outs = [o.cpu().numpy() for o in batch.run(use_graph=True)]
     _, F, _ = batch.ws.status()
+    assert F == min(expected_F(cfg, im, st) for im, st in zip(imgs, steps))
     rng = np.random.default_rng(79)
     for b, (im, st, out) in enumerate(zip(imgs, steps, outs)):
         H, W = im.shape
@@ -169,6 +170,7 @@ def test_full_isotropic_batch_matches_oracle():
     outs = [o.cpu().numpy() for o in batch.run(use_graph=True)]
     flags, F, _ = batch.ws.status()
     assert flags == 0
+    assert F == min(expected_F(cfg, im, st) for im, st in zip(imgs, steps))
     rng = np.random.default_rng(83)
     for b, (im, st, out) in enumerate(zip(imgs, steps, outs)):
         H, W = im.shape
