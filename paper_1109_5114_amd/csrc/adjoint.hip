@@ -25,9 +25,9 @@
 // non-parallel directions meet at every lattice point at most once, and
 // further factors only spread mass) on the rectangle that holds its support,
 // and the sum of those rectangles, a 2-D prefix sum of a difference array, is
-// maximised over the image.  Fg = 61 - ceil(log2 max|g|) - ceil(log2 bound),
-// unclamped, so the weights keep their bits whatever the scale of g.  The
-// only error is the rounding of omega_J.
+// maximised over the image.  Fg = 62 - ceil(log2(max|g| * bound)), unclamped,
+// so the weights keep their bits whatever the scale of g.  The only error is
+// the rounding of omega_J.
 #include "bsf_common.h"
 #include "cluster_box.h"
 
@@ -59,7 +59,8 @@ __device__ __forceinline__ bool scatters(float g) { return g != 0.0f && fabsf(g)
 __global__ void k_adj_begin(int32_t *status) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         status[ST_G_ABSMAX_BITS] = 0;
-        status[ST_COLSUM_E] = -0x40000000;
+        status[ST_COLSUM_MAX] = 0;
+        status[ST_COLSUM_MAX + 1] = 0;
         status[ST_G_NONFINITE] = 0;
     }
 }
@@ -98,39 +99,94 @@ __global__ __launch_bounds__(256) void k_adj_gmax(const float *__restrict__ g, i
     }
 }
 
-// ceil(log2 v) for v >= 1, exact for every 64-bit value.
-__device__ __forceinline__ int ceil_log2_u64(uint64_t v) { return v <= 1 ? 0 : 64 - __builtin_clzll(v - 1); }
+// Peak bound of the 1-D factor kernels.  For a continuous step s (clamped to
+// >= 1), R = floor((s - 1)/2) and lambda = (s - 2R - 1)/2, the normalised
+// factor is phi = alpha U + beta V with U, V the normalised odd boxes of
+// lengths 2R + 1 and 2R + 3, alpha = (1 - lambda)(2R + 1)/s, beta =
+// lambda (2R + 3)/s; max phi = 1/s, and phi * phi (symmetric) peaks at
+// sum phi^2 = (2R + 1 + 2 lambda^2)/s^2.  ||U * U||_2 = sqrt((2L^2 + 1)/(3L^3))
+// for a box of odd length L, so ||phi * phi||_2 <= (alpha sqrt||U*U|| +
+// beta sqrt||V*V||)^2 by the triangle and Cauchy-Schwarz inequalities.
+struct FactorBound {
+    double peak1;  // max phi
+    double peak2;  // max phi * phi = ||phi||_2^2
+    double l2sq2;  // bound on ||phi * phi||_2^2
+};
+
+__device__ __forceinline__ double box2_norm(double L) { return sqrt((2.0 * L * L + 1.0) / (3.0 * L * L * L)); }
+
+__device__ __forceinline__ FactorBound factor_bound(float s) {
+    const double sd = (double)s;
+    const double R = floor((sd - 1.0) * 0.5), lam = (sd - 2.0 * R - 1.0) * 0.5;
+    const double L = 2.0 * R + 1.0;
+    const double al = (1.0 - lam) * L / sd, be = lam * (L + 2.0) / sd;
+    const double m = al * sqrt(box2_norm(L)) + be * sqrt(box2_norm(L + 2.0));
+    FactorBound b;
+    b.peak1 = 1.0 / sd;
+    b.peak2 = (L + 2.0 * lam * lam) / (sd * sd);
+    b.l2sq2 = m * m * m * m;
+    return b;
+}
 
 // Column-sum bound, first part: each scattering pixel adds ceil(kmax 2^24) on
 // the rectangle of the image that holds its kernel's support, as the four
 // corners of a difference array D[(H + 1) x (W + 1)].  Along factor j the
-// kernel reaches |i| <= R_j + 1 lattice steps (R_j = floor((s_j - 1)/2)).
+// kernel reaches |i| <= R_j + 1 lattice steps.  kmax bounds the pixel's
+// kernel, the convolution of the direction kernels A_k (each the convolution
+// of its factors), by the smallest of
+//   - max A_a max A_b for two directions (factors of non-parallel directions
+//     meet at a lattice point at most once; further factors only spread mass),
+//   - ||A_a * A_b||_2 ||A_c * A_d||_2 = sqrt(prod ||A||_2^2) over up to four
+//     directions (Cauchy-Schwarz), and 1;
+// max A_k is at most 1/s of any of its factors, and max(phi * phi) of a
+// repeated (tied) factor; ||A_k||_2^2 is at most ||phi||_2^2 of any factor and
+// the bound on ||phi * phi||_2^2 of a repeated one.
 __global__ __launch_bounds__(256) void k_adj_colsum_scatter(AdjointArgs a, uint64_t *__restrict__ D) {
     int64_t x, y;
     if (!pixel_of_thread(a.H, a.W, x, y)) return;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     if (!scatters(a.gout[idx])) return;
-    float S[BSF_MAX_DIRS];
-    for (int k = 0; k < a.n_dirs; ++k) S[k] = 1.0f;
+    double pk[BSF_MAX_DIRS], l2[BSF_MAX_DIRS];
     int64_t ex = 0, ey = 0;
-    for (int j = 0; j < a.M; ++j) {
-        const float s = clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
-        const int k = j / a.order;
-        S[k] = fmaxf(S[k], s);
-        const int64_t reach = (int64_t)floorf((s - 1.0f) * 0.5f) + 1;
-        ex += reach * a.adx[k];
-        ey += reach * a.ady[k];
-    }
-    float s1 = 1.0f, s2 = 1.0f;  // the two largest direction steps
     for (int k = 0; k < a.n_dirs; ++k) {
-        if (S[k] > s1) {
-            s2 = s1;
-            s1 = S[k];
-        } else if (S[k] > s2) {
-            s2 = S[k];
+        pk[k] = 1.0;
+        l2[k] = 1.0;
+        for (int q = 0; q < a.order; ++q) {
+            const int j = k * a.order + q;
+            const float s = clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
+            const FactorBound fb = factor_bound(s);
+            pk[k] = fmin(pk[k], fb.peak1);
+            l2[k] = fmin(l2[k], fb.peak2);
+            if (a.tied && a.order >= 2) {
+                pk[k] = fmin(pk[k], fb.peak2);
+                l2[k] = fmin(l2[k], fb.l2sq2);
+            }
+            const int64_t reach = (int64_t)floorf((s - 1.0f) * 0.5f) + 1;
+            ex += reach * a.adx[k];
+            ey += reach * a.ady[k];
         }
     }
-    const double kmax = 1.0 / ((double)s1 * (double)s2);
+    // the two smallest peaks, and the product of up to four smallest L2 norms
+    double p1 = 1.0, p2 = 1.0;
+    for (int k = 0; k < a.n_dirs; ++k) {
+        if (pk[k] < p1) {
+            p2 = p1;
+            p1 = pk[k];
+        } else if (pk[k] < p2) {
+            p2 = pk[k];
+        }
+    }
+    double lprod = 1.0;
+    bool used[BSF_MAX_DIRS] = {};
+    for (int n = 0; n < 4 && n < a.n_dirs; ++n) {
+        int best = -1;
+        for (int k = 0; k < a.n_dirs; ++k)
+            if (!used[k] && (best < 0 || l2[k] < l2[best])) best = k;
+        used[best] = true;
+        lprod *= l2[best];
+    }
+    double kmax = fmin(1.0, fmin(p1 * p2, sqrt(lprod)));
+    kmax *= 1.0 + 0x1p-30;  // stays an upper bound through the rounding above
     const uint64_t v = (uint64_t)ceil(__builtin_ldexp(kmax, kKmaxBits));
     const int64_t W1 = a.W + 1;
     const int64_t x0 = max(x - ex, (int64_t)0), x1 = min(x + ex, a.W - 1) + 1;
@@ -142,37 +198,36 @@ __global__ __launch_bounds__(256) void k_adj_colsum_scatter(AdjointArgs a, uint6
 }
 
 // Column-sum bound, last part: after the 2-D prefix sum D(p) bounds
-// 2^24 sum_x k_x(p - x); its largest ceil(log2) over the image, minus 24.
+// 2^24 sum_x k_x(p - x); its largest value over the image.
 __global__ __launch_bounds__(256) void k_adj_colsum_max(const uint64_t *__restrict__ D, int64_t H, int64_t W,
                                                         int32_t *status) {
-    __shared__ int s_e[4];
-    int e = -0x40000000;
+    __shared__ uint64_t s_m[4];
+    uint64_t m = 0;
     const int64_t W1 = W + 1;
     for (int64_t y = blockIdx.x; y < H; y += gridDim.x)
-        for (int64_t x = threadIdx.x; x < W; x += blockDim.x) {
-            const uint64_t v = D[y * W1 + x];
-            if (v) e = max(e, ceil_log2_u64(v) - kKmaxBits);
-        }
-    for (int d = 32; d >= 1; d >>= 1) e = max(e, __shfl_xor(e, d, 64));
-    if ((threadIdx.x & 63) == 0) s_e[threadIdx.x >> 6] = e;
+        for (int64_t x = threadIdx.x; x < W; x += blockDim.x) m = max(m, D[y * W1 + x]);
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint64_t)__shfl_xor((unsigned long long)m, d, 64));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) e = max(e, s_e[k]);
-        atomicMax(&status[ST_COLSUM_E], e);
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = max(m, s_m[k]);
+        atomicMax(reinterpret_cast<unsigned long long *>(status + ST_COLSUM_MAX), (unsigned long long)m);
     }
 }
 
 __global__ void k_adj_choose_Fg(int32_t *status) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const float gmax = __uint_as_float((unsigned)status[ST_G_ABSMAX_BITS]);
-    const int eb = status[ST_COLSUM_E];
+    const uint64_t dmax = *reinterpret_cast<const uint64_t *>(status + ST_COLSUM_MAX);
     int Fg = 0;
-    if (gmax > 0.0f && eb > -0x40000000) {
+    if (gmax > 0.0f && dmax > 0) {
+        // |V| <= 2 * 2^Fg * max|g| * max_p sum_x k_x(p - x) < 2^63, and every
+        // |omega| <= 2^Fg max|g| kmax stays below that too
+        const double P = (double)gmax * __builtin_ldexp((double)dmax, -kKmaxBits) * (1.0 + 0x1p-40);
         int e;
-        const double m = __builtin_frexp((double)gmax, &e);
-        const int eg = (m == 0.5) ? e - 1 : e;  // |g| <= 2^eg
-        // |V| <= 2 * 2^Fg * 2^eg * 2^eb <= 2^62; every |omega| <= 2^Fg 2^eg 2^eb too
-        Fg = 61 - eg - eb;
+        const double m = __builtin_frexp(P, &e);
+        const int ceil_log2_P = (m == 0.5) ? e - 1 : e;
+        Fg = 62 - ceil_log2_P;
     }
     status[ST_FG] = Fg;
 }

@@ -170,8 +170,8 @@ bsf_status run_bound(const Plan &p, const Src &src, const float *steps, int32_t 
 enum AdjStatusWord : int {
     ST_G_ABSMAX_BITS = 16,  // scratch: float bits of max |gout| over the finite values
     ST_FG = 17,             // fixed-point bits of the scattered adjoint weights
-    ST_COLSUM_E = 18,       // scratch: ceil(log2) of the bound on sum_x k_x(p - x), max over p
-    ST_G_NONFINITE = 19,    // this backward call saw a NaN or infinite upstream gradient
+    ST_G_NONFINITE = 18,    // this backward call saw a NaN or infinite upstream gradient
+    ST_COLSUM_MAX = 20,     // scratch, 64 bits (words 20-21): max over p of 2^24 * the bound on sum_x k_x(p - x)
 };
 
 struct AdjointArgs {
