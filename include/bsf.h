@@ -282,6 +282,32 @@ bsf_status bsf_read_device_status(void *ws, void *stream, uint32_t *flags, int32
 
 const char *bsf_status_string(bsf_status s);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the forward
+ * filter of bsf_filter_varying with the same arguments and results, but with
+ * no workspace argument and no saved running sums.  The library keeps one
+ * scratch array of BSF_NOALLOC_SCRATCH_BYTES in device memory per GPU (a
+ * static device symbol, resident from the library's load until the process
+ * ends; its address is looked up once per device, with that device current),
+ * which holds the status words, the running-sum window and the scan carries.
+ *   status_out: nullable device int32[4]; receives this call's flags
+ *               (BSF_FLAG_*), F_used, log2_bound and 0.  The flags are cleared
+ *               at the start of every call.
+ * Returns BSF_E_WORKSPACE, before anything is enqueued, when the call needs more
+ * than BSF_NOALLOC_SCRATCH_BYTES (bsf_geometry.workspace_bytes of the same
+ * configuration and size), and BSF_E_DEVICE when the scratch address cannot be
+ * looked up.  Calls nothing that allocates.  Every call on a GPU shares that
+ * GPU's scratch array, which keeps the last call's contents: calls that overlap
+ * in time on one GPU (other streams, other host threads) race and must not be
+ * issued; calls in order on one stream are safe.  The stream's device must be
+ * the current device.
+ */
+#define BSF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+bsf_status bsf_filter_varying_noalloc(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H,
+                                      int64_t W, int64_t pitch, const float *steps, float *out, int64_t *out_num,
+                                      int64_t *out_den, float *dout_dsteps, int32_t *status_out, void *stream);
+
 /* Library version string, e.g. "bsf 0.1 gfx950". */
 const char *bsf_version(void);
 

@@ -55,7 +55,8 @@ EXPORTS = ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_var
            "bsf_forward_prepare", "bsf_forward_apply",
            "bsf_backward_workspace_bytes", "bsf_filter_backward", "bsf_batched_workspace_bytes",
            "bsf_filter_batched", "bsf_set_tuning", "bsf_get_tuning", "bsf_read_device_status",
-           "bsf_status_string", "bsf_version")
+           "bsf_status_string", "bsf_version", "bsf_filter_varying_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def lib():
@@ -85,13 +86,14 @@ def lib():
         L.bsf_get_tuning.restype = None
         L.bsf_read_device_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
+        L.bsf_filter_varying_noalloc.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, P, P, P]
         L.bsf_status_string.argtypes = [i32]
         L.bsf_status_string.restype = ctypes.c_char_p
         L.bsf_version.restype = ctypes.c_char_p
         for name in ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_varying",
                      "bsf_forward_prepare", "bsf_forward_apply",
                      "bsf_filter_backward", "bsf_filter_batched", "bsf_set_tuning",
-                     "bsf_read_device_status"):
+                     "bsf_read_device_status", "bsf_filter_varying_noalloc"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -273,6 +275,28 @@ def filter_varying(cfg: Config, img: torch.Tensor, steps: torch.Tensor, out: Opt
     if save_G:
         res.append(G)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def filter_varying_noalloc(cfg: Config, img: torch.Tensor, steps: torch.Tensor, out: torch.Tensor,
+                           num: Optional[torch.Tensor] = None, den: Optional[torch.Tensor] = None,
+                           dsteps: Optional[torch.Tensor] = None, status_out: Optional[torch.Tensor] = None):
+    """The forward filter through bsf_filter_varying_noalloc: no workspace, the
+    library's per-GPU static scratch (at most NOALLOC_SCRATCH_BYTES of window,
+    carries and status).  Every output tensor is passed in; status_out (int32
+    [4], device) receives this call's flags, F_used and log2_bound."""
+    _check_image(img)
+    H, W = img.shape
+    _check_steps(cfg, steps, H, W)
+    if status_out is not None and (status_out.dtype != torch.int32 or status_out.numel() < 4
+                                   or not status_out.is_cuda):
+        raise ValueError("status_out must be an int32 device tensor of 4 entries")
+    if dsteps is not None:
+        _check_steps(cfg, dsteps, H, W)
+    _check(lib().bsf_filter_varying_noalloc(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, _pitch(img),
+                                            _ptr(steps), _ptr(out), _ptr(num), _ptr(den), _ptr(dsteps),
+                                            _ptr(status_out), _stream(img.device)),
+           "bsf_filter_varying_noalloc")
+    return out
 
 
 def forward_prepare(cfg: Config, img: torch.Tensor, steps: torch.Tensor, ws: Workspace,

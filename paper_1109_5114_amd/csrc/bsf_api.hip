@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "bsf_common.h"
 
 namespace bsf {
@@ -405,6 +407,73 @@ bsf_status bsf_read_device_status(void *ws, void *stream, uint32_t *flags, int32
     if (clear) {
         int32_t z = 0;
         BSF_HIP_CHECK(hipMemcpy(ws, &z, sizeof(z), hipMemcpyHostToDevice));
+    }
+    return BSF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of bsf_filter_varying_noalloc: one array per GPU, in the code object
+// (no allocation at run time).  Host code never uses the symbol's name as an
+// address: the device address is looked up once per device and kept.
+__device__ __align__(256) unsigned char scratch[BSF_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mutex;
+
+bsf_status scratch_of_current_device(void **ptr) {
+    int dev = -1;
+    BSF_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return BSF_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        BSF_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return BSF_E_DEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return BSF_OK;
+}
+
+__global__ void k_copy_status(const int32_t *status, int32_t *out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        out[0] = status[ST_FLAGS];
+        out[1] = status[ST_F_USED];
+        out[2] = status[ST_LOG2_BOUND];
+        out[3] = 0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+bsf_status bsf_filter_varying_noalloc(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
+                                      int64_t pitch, const float *steps, float *out, int64_t *out_num,
+                                      int64_t *out_den, float *dout_dsteps, int32_t *status_out, void *stream) {
+    Plan p;
+    bsf_status r = make_plan(cfg, H, W, &p);
+    if (r != BSF_OK) return r;
+    if (ws_bytes_for(p, true) > BSF_NOALLOC_SCRATCH_BYTES) return BSF_E_WORKSPACE;
+    r = apply_checks(p, dtype, out_num, out_den, dout_dsteps);
+    if (r != BSF_OK) return r;
+    void *ws = nullptr;
+    r = scratch_of_current_device(&ws);
+    if (r != BSF_OK) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // this call's flags only: the array keeps the previous call's words
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, static_cast<int32_t *>(ws));
+    BSF_HIP_CHECK(hipGetLastError());
+    r = bsf_filter_varying(cfg, dtype, img, H, W, pitch, steps, out, out_num, out_den, dout_dsteps, nullptr, ws,
+                           BSF_NOALLOC_SCRATCH_BYTES, stream);
+    if (r != BSF_OK) return r;
+    if (status_out) {
+        hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, st, static_cast<const int32_t *>(ws), status_out);
+        BSF_HIP_CHECK(hipGetLastError());
     }
     return BSF_OK;
 }

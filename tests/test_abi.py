@@ -213,3 +213,17 @@ def test_batched_entry_point_validates_before_launch():
     assert L.bsf_filter_batched(ctypes.byref(c_bad), 2, d, ws, need, None, 0) == bsf.E_UNSUPPORTED
     # workspace one byte short
     assert L.bsf_filter_batched(ctypes.byref(c), 2, d, ws, need - 1, None, 0) == bsf.E_WORKSPACE
+
+
+def test_noalloc_entry_point_rejects_oversize_before_any_launch():
+    """bsf_filter_varying_noalloc checks its static scratch limit on the host
+    (no device call is reached for an oversize request)."""
+    L = bsf.lib()
+    cfg = bsf.Config(order=2, max_step=48.0)
+    assert bsf.plan(cfg, 4096, 4096).workspace_bytes > bsf.NOALLOC_SCRATCH_BYTES
+    rc = L.bsf_filter_varying_noalloc(ctypes.byref(cfg.c()), bsf.F32, None, 4096, 4096, 4096, None, None, None,
+                                      None, None, None, None)
+    assert rc == bsf.E_WORKSPACE
+    rc = L.bsf_filter_varying_noalloc(ctypes.byref(bsf.Config(order=0).c()), bsf.F32, None, 8, 8, 8, None, None,
+                                      None, None, None, None, None)
+    assert rc == bsf.E_INVALID
