@@ -86,13 +86,13 @@ typedef enum { BSF_ARITH_EXACT = 0, BSF_ARITH_FP64 = 1 } bsf_arith;
 
 /*
  * Filter configuration.
- *   dirs:      n_dirs primitive integer vectors (dx, dy), x = column, y = row,
- *              in canonical sign (dx > 0, or dx == 0 and dy > 0).  The running
- *              sums are taken in the order given.  At most one direction may have
- *              dy < 0 and it must come last: the running sums are kept on a
- *              finite window, and only the last pass may leave terms behind
- *              at the window edge (they are constant, or of degree < order, along
- *              its own direction, so its differences cancel them exactly).
+ *   dirs:      n_dirs distinct primitive integer vectors (dx, dy), x = column,
+ *              y = row, in canonical sign (dx > 0, or dx == 0 and dy > 0), e.g.
+ *              (1,0), (0,1), (1,1), (1,-1) for the box spline of Section 1.1 or
+ *              (2,1), (1,2), (1,-2), (2,-1) for the one of Alg. 3 and Table 1.
+ *              The running sums are taken in the order given, each line started
+ *              at zero where it enters the finite window; what that leaves out is
+ *              cancelled exactly by the taps' differences along every direction.
  *   order:     r >= 1 (box spline convolved r times); n_dirs * order <= 16.
  *   tied:      1: one step plane per direction, 0: one plane per box factor.
  *   mode:      BSF_STEPS_INT (integer steps, exact integer output) or
@@ -256,6 +256,28 @@ typedef struct {
 size_t bsf_batched_workspace_bytes(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs);
 bsf_status bsf_filter_batched(const bsf_config *cfg, int32_t B, const bsf_image_desc *descs,
                               void *ws, size_t ws_bytes, void *stream, int32_t use_graph);
+
+/*
+ * Steps from a covariance field (Section 1.1, eq. cov and eq. geometry; the
+ * minimum-kurtosis scales of Section 2.3), for a configuration of four
+ * directions (any four that span the 2x2 covariances: those of Section 1.1,
+ * those of Alg. 3).  cov: FP32 [3][H][W], the planes C11, C12, C22 of each
+ * pixel's target covariance in pixel units (x = column, y = row).  sub is
+ * subtracted from C11 and C22 first (Alg. 1 step 4 subtracts sigma^2 I).  Each
+ * of the r copies of an order-r filter carries C / r.  The scales a_k of the box
+ * spline with covariance sum_k (a_k^2 / 12) uhat_k uhat_k^T are, in lattice steps
+ * s_k = a_k / |u_k|, the non-negative solution with the smallest Frobenius norm
+ * of the kurtosis matrix sum_k a_k^4 uhat_k uhat_k^T; steps are floored at 1 and
+ * written to steps [planes][H][W] (tied: one plane per direction; untied: the
+ * same step on the r planes of a direction).  A covariance that is not
+ * positive definite, not finite, or too elongated for the directions at its
+ * orientation (beyond eq. boundE for those of Section 1.1) gets the scales
+ * that keep the smallest A_k = s_k^2 / 12 largest, and BSF_FLAG_RANGE, as do
+ * steps above max_step (clamped).  ws: at least 256 bytes (the status block).
+ * BSF_E_UNSUPPORTED unless n_dirs == 4.
+ */
+bsf_status bsf_cov_to_steps(const bsf_config *cfg, const float *cov, int64_t H, int64_t W, float sub, float *steps,
+                            void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Launch shapes (process-wide; set them before sizing workspaces and

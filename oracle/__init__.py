@@ -19,7 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-U8, U16, F32 = 1, 2, 3
+U8, U16, F32, F64 = 1, 2, 3, 4
 INT, REAL = 0, 1
 
 _lib = None
@@ -43,6 +43,15 @@ def lib():
         L.bsfo_grad_real.argtypes = [P, l, l, l, i, P, i, i, P, P, P, l, l, l, l, l, P, P, i]
         L.bsfo_preintegrate.argtypes = [P, i, l, l, l, i, P, i, i, l, l, l, l, P]
         L.bsfo_num_threads.argtypes = []
+        L.bsfo_cov_to_steps.argtypes = [P, i, d, d, d, P]
+        L.bsfo_cov_to_steps_field.argtypes = [P, i, l, P, d, P, P]
+        L.bsfo_orientation.argtypes = [d, d, d]
+        L.bsfo_orientation.restype = d
+        L.bsfo_elongation_bound.argtypes = [d]
+        L.bsfo_elongation_bound.restype = d
+        L.bsfo_condition2_bound.argtypes = [d, d, d]
+        L.bsfo_condition2_bound.restype = d
+        L.bsfo_bank_of.argtypes = [d]
         _lib = L
     return _lib
 
@@ -58,7 +67,9 @@ def _dtype_code(img):
         return U16
     if img.dtype == np.float32:
         return F32
-    raise TypeError("oracle images are uint8, uint16 or float32")
+    if img.dtype == np.float64:
+        return F64
+    raise TypeError("oracle images are uint8, uint16, float32 or float64")
 
 
 def num_threads():
@@ -212,3 +223,50 @@ def preintegrate(img, dirs, order, F, pads):
     if rc:
         raise ValueError(rc)
     return G
+
+
+# ----------------------------------------------------------------------------- covariance -> steps
+
+BANK1 = ((1, 0), (0, 1), (1, 1), (1, -1))      # the four directions of Section 1.1
+BANK2 = ((2, 1), (1, 2), (1, -2), (2, -1))     # those of Alg. 3 / Table 1, canonical sign
+
+
+def cov_to_steps(dirs, order, c11, c12, c22):
+    """Minimum-kurtosis steps (one per direction) of the box spline along four
+    integer directions with covariance C; returns (steps[4], infeasible)."""
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1))
+    out = np.zeros(4)
+    r = lib().bsfo_cov_to_steps(_p(d), int(order), float(c11), float(c12), float(c22), _p(out))
+    if r < 0:
+        raise ValueError("degenerate directions")
+    return out, bool(r)
+
+
+def cov_to_steps_field(dirs, order, cov, sub=0.0):
+    """cov [3][H][W] float32 (C11, C12, C22) -> steps [4][H][W] float64 and
+    the per-pixel infeasibility flags [H][W]."""
+    cov = np.ascontiguousarray(cov, dtype=np.float32)
+    _, H, W = cov.shape
+    n = H * W
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1))
+    steps = np.zeros((4, n))
+    flags = np.zeros(n, dtype=np.int32)
+    if lib().bsfo_cov_to_steps_field(_p(d), int(order), n, _p(cov), float(sub), _p(steps), _p(flags)):
+        raise ValueError("degenerate directions")
+    return steps.reshape(4, H, W), flags.reshape(H, W)
+
+
+def orientation(c11, c12, c22):
+    return lib().bsfo_orientation(float(c11), float(c12), float(c22))
+
+
+def elongation_bound(phi):
+    return lib().bsfo_elongation_bound(float(phi))
+
+
+def condition2_bound(c11, c12, c22):
+    return lib().bsfo_condition2_bound(float(c11), float(c12), float(c22))
+
+
+def bank_of(phi):
+    return lib().bsfo_bank_of(float(phi))

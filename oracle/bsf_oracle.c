@@ -52,7 +52,7 @@
 #include <omp.h>
 #endif
 
-enum { BSFO_U8 = 1, BSFO_U16 = 2, BSFO_F32 = 3 };
+enum { BSFO_U8 = 1, BSFO_U16 = 2, BSFO_F32 = 3, BSFO_F64 = 4 };
 enum { BSFO_INT = 0, BSFO_REAL = 1 };
 
 #define BSFO_MAX_FACTORS 16
@@ -64,6 +64,7 @@ static double img_at(const void *img, int dtype, long H, long W, long pitch, lon
     switch (dtype) {
     case BSFO_U8: return (double)((const uint8_t *)img)[y * pitch + x];
     case BSFO_U16: return (double)((const uint16_t *)img)[y * pitch + x];
+    case BSFO_F64: return ((const double *)img)[y * pitch + x];
     default: return (double)((const float *)img)[y * pitch + x];
     }
 }
@@ -341,7 +342,7 @@ int bsfo_filter(const void *img, int dtype, long H, long W, long pitch,
                 d *= si[j];
             }
             kern_i64 K = pixel_kernel_int(M, fdx, fdy, si);
-            if (dtype == BSFO_F32) {
+            if (dtype == BSFO_F32 || dtype == BSFO_F64) {
                 double acc = 0.0;
                 for (long b = 0; b < K.h; b++)
                     for (long a = 0; a < K.w; a++) {
@@ -520,6 +521,213 @@ int bsfo_preintegrate(const void *img, int dtype, long H, long W, long pitch,
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Scales from a covariance: eq. cov gives the covariance of a box spline as   */
+/* sum_k (a_k^2 / 12) u_k u_k^T over its unit directions, i.e. sum_k          */
+/* (s_k^2 / 12) u_k u_k^T with s_k counted in lattice steps along the integer  */
+/* vector u_k; four directions leave one free parameter, fixed by the minimum  */
+/* kurtosis: the Frobenius norm of sum_k a_k^4 uhat_k uhat_k^T (the matrix of  */
+/* Section 2.3 for the directions of Alg. 3, the same construction for the     */
+/* directions of Section 1.1), which is sum_k A_k^2 |u_k|^2 u_k u_k^T up to a  */
+/* constant, A_k = s_k^2 / 12.                                                 */
+/* ------------------------------------------------------------------------- */
+
+static double frob2_kurtosis(const int *dirs, const double A[4])
+{
+    double k11 = 0, k12 = 0, k22 = 0;
+    for (int k = 0; k < 4; k++) {
+        double ux = dirs[2 * k], uy = dirs[2 * k + 1], n2 = ux * ux + uy * uy;
+        k11 += A[k] * A[k] * n2 * ux * ux;
+        k12 += A[k] * A[k] * n2 * ux * uy;
+        k22 += A[k] * A[k] * n2 * uy * uy;
+    }
+    return k11 * k11 + 2 * k12 * k12 + k22 * k22;
+}
+
+static double det3(double a[3][3])
+{
+    return a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1])
+         - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0])
+         + a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+}
+
+/* Steps s[4] (lattice steps, one per direction, the same for the `order`
+ * copies of a direction, each copy carrying C / order) of the minimum-kurtosis
+ * box spline along the four integer directions dirs with covariance C.
+ * Returns 0, or 1 when no non-negative scales reproduce C (the elongation
+ * exceeds what the directions allow): then the choice maximising the smallest
+ * A_k is taken, negative parts dropped.  Steps are floored at 1 (a box of one
+ * lattice step is the identity).  -1 for degenerate directions. */
+int bsfo_cov_to_steps(const int *dirs, int order, double c11, double c12, double c22, double *steps)
+{
+    double c[3] = {c11 / order, c12 / order, c22 / order};
+    double m[3][4];
+    for (int k = 0; k < 4; k++) {
+        double ux = dirs[2 * k], uy = dirs[2 * k + 1];
+        m[0][k] = ux * ux;
+        m[1][k] = ux * uy;
+        m[2][k] = uy * uy;
+    }
+    /* null vector by cofactors, and a particular solution from the best-
+     * conditioned three columns */
+    double n[4], A0[4] = {0, 0, 0, 0}, best = 0;
+    int skip_best = -1;
+    for (int k = 0; k < 4; k++) {
+        double sub[3][3];
+        for (int r = 0; r < 3; r++)
+            for (int q = 0, cc = 0; q < 4; q++)
+                if (q != k) sub[r][cc++] = m[r][q];
+        double d = det3(sub);
+        n[k] = (k % 2 ? -1.0 : 1.0) * d;
+        if (fabs(d) > best) {
+            best = fabs(d);
+            skip_best = k;
+        }
+    }
+    if (skip_best < 0) return -1;
+    {
+        /* Cramer's rule on the columns other than skip_best */
+        int cols[3], cc = 0;
+        double sub[3][3];
+        for (int q = 0; q < 4; q++)
+            if (q != skip_best) cols[cc++] = q;
+        for (int r = 0; r < 3; r++)
+            for (int q = 0; q < 3; q++) sub[r][q] = m[r][cols[q]];
+        double d = det3(sub);
+        for (int q = 0; q < 3; q++) {
+            double t[3][3];
+            memcpy(t, sub, sizeof(t));
+            for (int r = 0; r < 3; r++) t[r][q] = c[r];
+            A0[cols[q]] = det3(t) / d;
+        }
+    }
+    /* feasible t: A0 + t n >= 0 */
+    double lo = -INFINITY, hi = INFINITY;
+    int infeasible = 0;
+    for (int k = 0; k < 4; k++) {
+        if (n[k] > 0) lo = fmax(lo, -A0[k] / n[k]);
+        else if (n[k] < 0) hi = fmin(hi, -A0[k] / n[k]);
+        else if (A0[k] < 0) infeasible = 1;
+    }
+    double A[4], tbest;
+    if (!infeasible && lo <= hi) {
+        /* dense scan of the quartic, then golden-section refinement */
+        const int N = 4096;
+        double fbest = INFINITY;
+        int ibest = 0;
+        for (int i = 0; i <= N; i++) {
+            double t = lo + (hi - lo) * i / N;
+            for (int k = 0; k < 4; k++) A[k] = A0[k] + t * n[k];
+            double f = frob2_kurtosis(dirs, A);
+            if (f < fbest) {
+                fbest = f;
+                ibest = i;
+            }
+        }
+        double a = lo + (hi - lo) * (ibest > 0 ? ibest - 1 : 0) / N;
+        double b = lo + (hi - lo) * (ibest < N ? ibest + 1 : N) / N;
+        const double g = (sqrt(5.0) - 1.0) / 2.0;
+        for (int it = 0; it < 200; it++) {
+            double t1 = b - g * (b - a), t2 = a + g * (b - a), f1, f2;
+            for (int k = 0; k < 4; k++) A[k] = A0[k] + t1 * n[k];
+            f1 = frob2_kurtosis(dirs, A);
+            for (int k = 0; k < 4; k++) A[k] = A0[k] + t2 * n[k];
+            f2 = frob2_kurtosis(dirs, A);
+            if (f1 <= f2) b = t2;
+            else a = t1;
+        }
+        tbest = 0.5 * (a + b);
+        for (int k = 0; k < 4; k++) A[k] = A0[k] + tbest * n[k];
+        if (frob2_kurtosis(dirs, A) > fbest) tbest = lo + (hi - lo) * ibest / N;
+        tbest = fmin(fmax(tbest, lo), hi);
+    } else {
+        /* maximise min_k A_k(t): the best of the crossings of two lines */
+        infeasible = 1;
+        double vbest = -INFINITY;
+        tbest = 0;
+        for (int i = 0; i < 4; i++)
+            for (int j = i + 1; j < 4; j++) {
+                if (n[i] == n[j]) continue;
+                double t = (A0[j] - A0[i]) / (n[i] - n[j]), v = INFINITY;
+                for (int k = 0; k < 4; k++) v = fmin(v, A0[k] + t * n[k]);
+                if (v > vbest) {
+                    vbest = v;
+                    tbest = t;
+                }
+            }
+    }
+    for (int k = 0; k < 4; k++) {
+        double Ak = fmax(A0[k] + tbest * n[k], 0.0);
+        steps[k] = fmax(sqrt(12.0 * Ak), 1.0);
+    }
+    return infeasible;
+}
+
+/* Orientation of C: the angle in [0, pi) of its top eigenvector (Section 1.1). */
+double bsfo_orientation(double c11, double c12, double c22)
+{
+    double phi = 0.5 * atan2(2.0 * c12, c11 - c22);
+    if (phi < 0) phi += M_PI;
+    if (phi >= M_PI) phi -= M_PI;
+    return phi;
+}
+
+/* eq. boundE: the largest elongation of the box spline of Section 1.1 at
+ * orientation phi; infinite along its axes. */
+double bsfo_elongation_bound(double phi)
+{
+    double sn = sin(phi), cs = cos(phi);
+    if (sn == 0.0 || cs == 0.0) return INFINITY;
+    double t = fabs(sn / cs - cs / sn) / 2.0;
+    double q = sqrt(1.0 + t * t);
+    if (1.0 + t - q <= 0.0) return INFINITY;
+    return (1.0 + t + q) / (1.0 + t - q);
+}
+
+/* condition2: sigma^2 below this keeps C - sigma^2 I a covariance the
+ * box spline of Section 1.1 can reach at C's orientation. */
+double bsfo_condition2_bound(double c11, double c12, double c22)
+{
+    double e = bsfo_elongation_bound(bsfo_orientation(c11, c12, c22));
+    double f = isinf(e) ? 1.0 : (e + 1.0) / (e - 1.0);
+    return 0.5 * (c11 + c22 - f * sqrt((c11 - c22) * (c11 - c22) + 4.0 * c12 * c12));
+}
+
+/* Sector of Alg. 2: 0 when phi is closer (modulo pi) to an axis of the first
+ * bank, 0, 45, 90, 135 degrees, than to one of the second, atan(1/2),
+ * atan(2), pi - atan(2), pi - atan(1/2); ties go to the first. */
+int bsfo_bank_of(double phi)
+{
+    const double a1[4] = {0.0, M_PI / 4, M_PI / 2, 3 * M_PI / 4};
+    const double a2[4] = {atan(0.5), atan(2.0), M_PI - atan(2.0), M_PI - atan(0.5)};
+    double d1 = INFINITY, d2 = INFINITY;
+    for (int k = 0; k < 4; k++) {
+        double d = fabs(phi - a1[k]);
+        d1 = fmin(d1, fmin(d, M_PI - d));
+        d = fabs(phi - a2[k]);
+        d2 = fmin(d2, fmin(d, M_PI - d));
+    }
+    return d2 < d1 ? 1 : 0;
+}
+
+/* The same over a field of n pixels: cov = [3][n] (C11, C12, C22), sub is
+ * subtracted from the diagonal first (Alg. 1 step 4); steps = [4][n]; flags[n]
+ * gets the return value of bsfo_cov_to_steps. */
+int bsfo_cov_to_steps_field(const int *dirs, int order, long n, const float *cov, double sub, double *steps,
+                            int *flags)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long i = 0; i < n; i++) {
+        double s[4];
+        int r = bsfo_cov_to_steps(dirs, order, (double)cov[i] - sub, (double)cov[n + i], (double)cov[2 * n + i] - sub, s);
+        if (r < 0) bad = 1;
+        flags[i] = r;
+        for (int k = 0; k < 4; k++) steps[k * n + i] = s[k];
+    }
+    return bad ? -1 : 0;
 }
 
 int bsfo_num_threads(void)

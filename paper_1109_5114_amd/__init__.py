@@ -55,7 +55,7 @@ EXPORTS = ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_var
            "bsf_forward_prepare", "bsf_forward_apply",
            "bsf_backward_workspace_bytes", "bsf_filter_backward", "bsf_batched_workspace_bytes",
            "bsf_filter_batched", "bsf_set_tuning", "bsf_get_tuning", "bsf_read_device_status",
-           "bsf_status_string", "bsf_version", "bsf_filter_varying_noalloc")
+           "bsf_status_string", "bsf_version", "bsf_filter_varying_noalloc", "bsf_cov_to_steps")
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -87,13 +87,14 @@ def lib():
         L.bsf_read_device_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
         L.bsf_filter_varying_noalloc.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, P, P, P]
+        L.bsf_cov_to_steps.argtypes = [cfgp, P, i64, i64, ctypes.c_float, P, P, sz, P]
         L.bsf_status_string.argtypes = [i32]
         L.bsf_status_string.restype = ctypes.c_char_p
         L.bsf_version.restype = ctypes.c_char_p
         for name in ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_varying",
                      "bsf_forward_prepare", "bsf_forward_apply",
                      "bsf_filter_backward", "bsf_filter_batched", "bsf_set_tuning",
-                     "bsf_read_device_status", "bsf_filter_varying_noalloc"):
+                     "bsf_read_device_status", "bsf_filter_varying_noalloc", "bsf_cov_to_steps"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -297,6 +298,24 @@ def filter_varying_noalloc(cfg: Config, img: torch.Tensor, steps: torch.Tensor, 
                                             _ptr(status_out), _stream(img.device)),
            "bsf_filter_varying_noalloc")
     return out
+
+
+def cov_to_steps(cfg: Config, cov: torch.Tensor, sub: float = 0.0, steps: Optional[torch.Tensor] = None,
+                 ws: Optional[Workspace] = None) -> torch.Tensor:
+    """Minimum-kurtosis steps of the configuration's four directions for a
+    covariance field cov (float32 [3][H][W]: C11, C12, C22), sub subtracted
+    from the diagonal first.  Returns steps float32 [planes][H][W]."""
+    if cov.dtype != torch.float32 or not cov.is_cuda or not cov.is_contiguous() or cov.dim() != 3 \
+            or cov.shape[0] != 3:
+        raise ValueError("cov must be a contiguous float32 [3][H][W] device tensor")
+    _, H, W = cov.shape
+    if steps is None:
+        steps = torch.empty((cfg.planes, H, W), dtype=torch.float32, device=cov.device)
+    _check_steps(cfg, steps, H, W)
+    ws = ws or _workspace(cov.device, 256)
+    _check(lib().bsf_cov_to_steps(ctypes.byref(cfg.c()), _ptr(cov), H, W, float(sub), _ptr(steps), ws.ptr(),
+                                  ws.nbytes, _stream(cov.device)), "bsf_cov_to_steps")
+    return steps
 
 
 def forward_prepare(cfg: Config, img: torch.Tensor, steps: torch.Tensor, ws: Workspace,

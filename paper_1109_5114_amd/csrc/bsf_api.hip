@@ -53,21 +53,23 @@ bsf_status make_plan(const bsf_config *cfg, int64_t H, int64_t W, Plan *p) {
     if (!(cfg->max_step >= 1.0f) || !isfinite(cfg->max_step) || cfg->max_step > 1.0e6f) return BSF_E_INVALID;
     if (cfg->frac_bits < -1 || cfg->frac_bits > 62) return BSF_E_INVALID;
     if (H < 0 || W < 0 || H > (int64_t(1) << 18) || W > (int64_t(1) << 18)) return BSF_E_INVALID;
-    int n_up = 0;
+    // Any directions, in any order: a line of a running sum starts at zero
+    // where it enters the window, and what that truncation leaves out is, on
+    // the window, a polynomial of degree < r along the pass's own lines,
+    // carried through the later passes in a form that every tap combination
+    // (r-th differences along every direction) cancels, as long as all taps
+    // lie in the window.
     for (int k = 0; k < cfg->n_dirs; ++k) {
         const int dx = cfg->dirs[2 * k], dy = cfg->dirs[2 * k + 1];
         if (dx == 0 && dy == 0) return BSF_E_INVALID;
         if (gcd_int(dx, dy) != 1) return BSF_E_INVALID;              // primitive
         if (dx < 0 || (dx == 0 && dy < 0)) return BSF_E_INVALID;     // canonical sign
         if (dx > 64 || dy > 64 || dy < -64) return BSF_E_INVALID;
-        if (dy < 0) {
-            ++n_up;
-            if (k != cfg->n_dirs - 1) return BSF_E_INVALID;          // only the last pass may be truncated
-        }
+        for (int l = 0; l < k; ++l)
+            if (p->dx[l] == dx && p->dy[l] == dy) return BSF_E_INVALID;  // each direction once
         p->dx[k] = dx;
         p->dy[k] = dy;
     }
-    if (n_up > 1) return BSF_E_INVALID;
     p->n_dirs = cfg->n_dirs;
     p->order = cfg->order;
     p->M = cfg->n_dirs * cfg->order;
@@ -380,6 +382,23 @@ bsf_status bsf_filter_backward(const bsf_config *cfg, int64_t H, int64_t W, cons
     }
     return run_adjoint_finish(p, static_cast<const int64_t *>(L.G), L.status, grad_img, gout, dout_dsteps,
                               grad_steps, st);
+}
+
+bsf_status bsf_cov_to_steps(const bsf_config *cfg, const float *cov, int64_t H, int64_t W, float sub, float *steps,
+                            void *ws, size_t ws_bytes, void *stream) {
+    Plan p;
+    bsf_status r = make_plan(cfg, H, W, &p);
+    if (r != BSF_OK) return r;
+    if (p.n_dirs != 4) return BSF_E_UNSUPPORTED;
+    if (!ws) return BSF_E_INVALID;
+    if (ws_bytes < kStatusBytes) return BSF_E_WORKSPACE;
+    if (H * W > 0 && (!cov || !steps)) return BSF_E_INVALID;
+    if (!isfinite(sub)) return BSF_E_INVALID;
+    CovBank b;
+    r = make_cov_bank(p, &b);
+    if (r != BSF_OK) return r;
+    return run_cov_to_steps(p, b, nullptr, cov, nullptr, sub, steps, nullptr, nullptr, static_cast<int32_t *>(ws),
+                            static_cast<hipStream_t>(stream));
 }
 
 bsf_status bsf_set_tuning(int32_t gather_wx, int32_t line_tl) {

@@ -194,6 +194,21 @@ bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *sta
 bsf_status run_adjoint_finish(const Plan &p, const int64_t *Ghat, const int32_t *status, float *grad_img,
                               const float *gout, const float *dsteps, float *grad_steps, hipStream_t st);
 
+// Covariance -> steps (cov.hip).  For a plan of four directions: n spans the
+// null space of A -> sum_k A_k u_k u_k^T, P maps (C11, C12, C22) to a
+// particular solution, w[e][k] = |u_k|^2 (u_k u_k^T)_e weighs K.
+struct CovBank {
+    double n[4];
+    double P[4][3];
+    double w[3][4];
+};
+bsf_status make_cov_bank(const Plan &p, CovBank *b);
+// steps1 (and steps2, sel with a second bank): planes of the plans' layout;
+// sub_dev (nullable, device float) or sub is subtracted from the diagonal.
+bsf_status run_cov_to_steps(const Plan &p, const CovBank &b1, const CovBank *b2, const float *cov,
+                            const float *sub_dev, float sub, float *steps1, float *steps2, uint8_t *sel,
+                            int32_t *status, hipStream_t st);
+
 }  // namespace bsf
 
 #define BSF_HIP_CHECK(expr)                                   \

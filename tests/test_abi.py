@@ -58,10 +58,11 @@ def test_plan_window_covers_every_tap():
     ((2, 4), (1, 0)),               # not primitive
     ((-1, 1),),                     # not canonical sign
     ((0, -1),),                     # not canonical sign
-    ((1, -1), (1, 0)),              # an upward direction that is not last
-    ((1, -1), (2, -1)),             # two upward directions
+    ((1, 0), (0, 1), (1, 0)),       # a direction twice
 ])
 def test_plan_rejects_bad_directions(dirs):
+    """Zero, non-primitive, non-canonical or repeated directions are refused
+    before anything runs."""
     with pytest.raises(bsf.BsfError) as e:
         geo(bsf.Config(dirs=dirs))
     assert e.value.code == bsf.E_INVALID
@@ -227,3 +228,18 @@ def test_noalloc_entry_point_rejects_oversize_before_any_launch():
     rc = L.bsf_filter_varying_noalloc(ctypes.byref(bsf.Config(order=0).c()), bsf.F32, None, 8, 8, 8, None, None,
                                       None, None, None, None, None)
     assert rc == bsf.E_INVALID
+
+
+@pytest.mark.parametrize("dirs", [
+    ((2, 1), (1, 2), (1, -2), (2, -1)),     # the directions of Alg. 3 / Table 1
+    ((1, -1), (1, 0), (0, 1), (1, 1)),      # an upward direction first
+    ((1, -2), (2, -1)),                     # upward directions only
+])
+def test_plan_accepts_upward_directions_anywhere(dirs):
+    g = geo(bsf.Config(dirs=dirs, order=2, max_step=9.0))
+    # every tap stays in the window: per direction r (R + 2) lattice steps back
+    # and r (R + 1) forward, R = 4
+    lo, hi = 2 * 6, 2 * 5
+    assert g.pad_left == sum(lo * dx for dx, dy in dirs)
+    assert g.pad_top == sum(lo * dy if dy > 0 else hi * -dy for dx, dy in dirs)
+    assert g.pad_bottom == sum(hi * dy if dy > 0 else lo * -dy for dx, dy in dirs)

@@ -32,6 +32,8 @@ def sample_pixels(H, W, n, seed):
     (np.uint16, ((1, 0), (0, 1)), 3, (21, 19), 0),
     (np.uint8, ((1, 1), (2, 1), (1, -2)), 1, (31, 26), 0),
     (np.float32, ((0, 1), (1, 0), (1, 1), (1, -1)), 2, (150, 9), 20),   # tall: many line tiles
+    (np.uint8, ((2, 1), (1, 2), (1, -2), (2, -1)), 2, (43, 57), 0),     # Alg. 3 directions
+    (np.uint16, ((1, -2), (1, 0), (2, -1), (0, 1)), 1, (60, 35), 0),    # upward passes first
 ])
 def test_preintegrate_bit_exact(dtype, dirs, order, shape, F):
     note("preintegrate", dtype.__name__, dirs, order, shape)
@@ -125,6 +127,39 @@ def test_continuous_tied_order2(shape, lo, hi, smooth):
     ref = O.filter(img, DIRS4, 2, True, O.REAL, steps)
     assert flags == 0
     assert_close(out, ref, F, what="real tied order2")
+
+
+BETA2 = ((2, 1), (1, 2), (1, -2), (2, -1))
+
+
+@pytest.mark.parametrize("order,mode,shape,hi", [
+    (1, "int", (41, 47), 9.0),
+    (2, "int", (23, 29), 5.0),
+    (1, "real", (52, 38), 11.0),
+    (2, "real", (37, 45), 9.0),
+])
+def test_alg3_directions(order, mode, shape, hi):
+    """The directions of Alg. 3 and Table 1, (2,1), (1,2), (-1,2), (-2,1) in
+    canonical sign, two of them upward: integer numerators bit for bit, float
+    outputs within the fixed-point bound."""
+    note("alg3 directions", order, mode, shape)
+    rng = np.random.default_rng(30 + order)
+    cfg = bsf.Config(dirs=BETA2, order=order, mode=bsf.STEPS_INT if mode == "int" else bsf.STEPS_REAL,
+                     max_step=hi)
+    if mode == "int":
+        img = rng.integers(0, 256, size=shape).astype(np.uint8)
+        steps = rng.integers(1, int(hi) + 1, size=(4,) + shape).astype(np.float32)
+        out, num, den, flags, F = run_forward(cfg, img, steps, want_num=True, want_den=True)
+        ref, rnum, rden = O.filter(img, BETA2, order, True, O.INT, steps, want_int=True)
+        np.testing.assert_array_equal(num, rnum)
+        np.testing.assert_array_equal(den, rden)
+    else:
+        img = rng.random(shape, dtype=np.float32)
+        steps = np.stack([WL.smooth(rng, *shape, 1.0, hi) for _ in range(4)]).astype(np.float32)
+        out, _, _, flags, F = run_forward(cfg, img, steps)
+        ref = O.filter(img, BETA2, order, True, O.REAL, steps)
+    assert flags == 0
+    assert_close(out, ref, F, quantised=mode != "int", what="alg3 directions")
 
 
 def test_continuous_untied_order2_generic():

@@ -409,6 +409,33 @@ def test_running_sums_and_signed_taps_reproduce_filter_int(order):
             assert _taps_int(G, pads, fdirs, svec, x, y) == num[y, x]
 
 
+@pytest.mark.parametrize("dirs", [
+    ((2, 1), (1, 2), (1, -2), (2, -1)),     # the directions of Alg. 3 / Table 1
+    ((1, -2), (2, -1), (2, 1), (1, 2)),     # both upward directions first
+    ((1, -1), (1, 0), (0, 1), (1, 1)),      # the anti-diagonal first
+])
+@pytest.mark.parametrize("order", [1, 2])
+def test_signed_taps_cancel_truncation_of_any_pass(dirs, order):
+    """Lines of every running sum start at zero where they enter the window;
+    what that leaves out is cancelled by the signed taps whichever passes point
+    upward and in whatever order they run, so the taps reproduce the integer
+    filter exactly for any direction set (the reading under which the library
+    accepts any canonical directions)."""
+    rng = np.random.default_rng(17 + order)
+    H, W = 11, 13
+    img = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    steps = rng.integers(1, 5, size=(4, H, W)).astype(np.float32)
+    reach = 2 * 4 * order * (4 + 1)
+    pads = (reach, reach, reach, reach)
+    G = O.preintegrate(img, dirs, order, 0, pads)
+    out, num, den = O.filter(img, dirs, order, True, O.INT, steps, want_int=True)
+    fdirs = [d for d in dirs for _ in range(order)]
+    for y in range(H):
+        for x in range(W):
+            svec = [int(steps[j // order, y, x]) for j in range(4 * order)]
+            assert _taps_int(G, pads, fdirs, svec, x, y) == num[y, x]
+
+
 def _table1():
     """Rows of tests/golden/table1_fd_mesh.txt: (cx[4], cy[4], sign)."""
     import os
