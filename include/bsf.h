@@ -280,6 +280,48 @@ bsf_status bsf_cov_to_steps(const bsf_config *cfg, const float *cov, int64_t H, 
                             void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Alg. 1 (Section 2.1, better accuracy): C = sigma^2 I + Delta C (eq. SigmaIso)
+ * with sigma^2 half the bound of condition2 (with e(phi) of eq. boundE at each
+ * pixel's orientation), taken as the smallest over the image because the
+ * first pass is one global convolution (Alg. 1 steps 1-3: the box spline of
+ * Section 1.1 with all four scales sqrt(6) sigma); then every pixel's
+ * minimum-kurtosis scales for C - sigma^2 I (step 4, as bsf_cov_to_steps) filter
+ * the first pass's output (step 5).  By Prop. 1 and Prop. 2 the result is one
+ * space-variant filter whose kernel at each pixel has covariance C.
+ *   cfg:  the four directions of Section 1.1 in any order, continuous steps;
+ *         order r (the paper's BoxFilter is r = 1; each pass uses r copies);
+ *         max_step bounds the steps of both passes.
+ *   img:  FP32 [H][pitch];  cov: FP32 [3][H][W] (C11, C12, C22);  out: FP32 [H][W].
+ *   ws:   at least bsf_alg1_workspace_bytes (status block first; it receives
+ *         the flags of both passes, F_used of the second, and sigma^2 in an
+ *         internal word).  The first pass's output is kept in FP32 in ws.
+ * BSF_E_UNSUPPORTED for other directions or integer steps.
+ */
+size_t bsf_alg1_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W);
+bsf_status bsf_filter_alg1(const bsf_config *cfg, const float *img, int64_t H, int64_t W, int64_t pitch,
+                           const float *cov, float *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Alg. 2 (Section 2.2, improved elongation): running sums of the image along
+ * both four-direction sets, (1,0), (0,1), (1,1), (1,-1) of Section 1.1 and
+ * (2,1), (1,2), (-1,2), (-2,1) of Alg. 3 (canonical sign (1,-2), (2,-1));
+ * each pixel's orientation (the top eigenvector of its C) picks the set whose
+ * axes lie nearer (the sectors S and S'; ties go to the first set), whose
+ * minimum-kurtosis scales for C (bsf_cov_to_steps) give its finite difference on
+ * that set's running sums.
+ *   cfg:      order, tied, continuous steps, max_step, frac_bits, arith; its
+ *             directions are not used.
+ *   img:      [H][pitch] of dtype;  cov: FP32 [3][H][W];  out: FP32 [H][W].
+ *   bank_out: nullable uint8 [H][W]: 0 or 1, the set each pixel used.
+ *   ws:       at least bsf_alg2_workspace_bytes (status block first: flags of
+ *             both sets, the smaller F).
+ */
+size_t bsf_alg2_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W);
+bsf_status bsf_filter_alg2(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
+                           int64_t pitch, const float *cov, float *out, uint8_t *bank_out, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/*
  * Launch shapes (process-wide; set them before sizing workspaces and
  * launching work, not concurrently with other calls):
  *   gather_wx  width in pixels of one wavefront's block in the tied order-2

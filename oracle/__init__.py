@@ -270,3 +270,56 @@ def condition2_bound(c11, c12, c22):
 
 def bank_of(phi):
     return lib().bsfo_bank_of(float(phi))
+
+
+def alg1(img, cov, order=1, sigma2=None, steps2=None):
+    """Alg. 1 written out with the oracle's pieces: sigma^2 = half the smallest
+    condition2 bound (unless given), the isotropic pass with scales
+    sqrt(6) sigma (sqrt(6 sigma^2 / r) lattice steps on the axes, sqrt(3 sigma^2 / r)
+    on the diagonals, floored at 1), then every pixel's minimum-kurtosis steps
+    for C - sigma^2 I (unless steps2 is given) on the first pass's FP64 output.
+    Returns (out, sigma2, steps1, steps2)."""
+    img = np.ascontiguousarray(img, dtype=np.float32)
+    H, W = img.shape
+    cov = np.ascontiguousarray(cov, dtype=np.float32)
+    if sigma2 is None:
+        b = np.array([condition2_bound(cov[0].flat[i], cov[1].flat[i], cov[2].flat[i]) for i in range(H * W)])
+        b = np.where(np.isfinite(b), np.maximum(b, 0.0), 0.0)
+        sigma2 = 0.5 * b.min()
+    axis = max(np.sqrt(6.0 * sigma2 / order), 1.0)
+    diag = max(np.sqrt(3.0 * sigma2 / order), 1.0)
+    steps1 = np.empty((4, H, W), dtype=np.float32)
+    for k, (dx, dy) in enumerate(BANK1):
+        steps1[k] = diag if dx and dy else axis
+    mid = filter(img, BANK1, order, True, REAL, steps1)
+    if steps2 is None:
+        steps2, _ = cov_to_steps_field(BANK1, order, cov, sub=sigma2)
+    out = filter(np.ascontiguousarray(mid), BANK1, order, True, REAL, np.asarray(steps2, dtype=np.float32))
+    return out, sigma2, steps1, steps2
+
+
+def alg2_banks(cov):
+    """The sector of Alg. 2 at every pixel: 0 for the box spline of Section
+    1.1, 1 for the one of Alg. 3."""
+    cov = np.asarray(cov, dtype=np.float32)
+    _, H, W = cov.shape
+    return np.array([bank_of(orientation(float(cov[0].flat[i]), float(cov[1].flat[i]), float(cov[2].flat[i])))
+                     for i in range(H * W)], dtype=np.uint8).reshape(H, W)
+
+
+def alg2(img, cov, order=2, steps=None):
+    """Alg. 2 written out: each pixel filtered by the box spline of its
+    sector with its minimum-kurtosis steps (or with steps = (steps_bank1,
+    steps_bank2) when given).  Returns (out, banks)."""
+    img = np.ascontiguousarray(img)
+    H, W = img.shape
+    banks = alg2_banks(cov)
+    if steps is None:
+        steps = (cov_to_steps_field(BANK1, order, cov)[0], cov_to_steps_field(BANK2, order, cov)[0])
+    out = np.zeros(H * W)
+    for bank, dirs, st in ((0, BANK1, steps[0]), (1, BANK2, steps[1])):
+        pix = np.flatnonzero(banks.reshape(-1) == bank)
+        if len(pix):
+            st = np.where(np.isfinite(st), np.maximum(st, 1.0), 1.0).astype(np.float32)
+            out[pix] = filter(img, dirs, order, True, REAL, st, pix=pix)
+    return out.reshape(H, W), banks

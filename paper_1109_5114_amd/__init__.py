@@ -55,7 +55,8 @@ EXPORTS = ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_var
            "bsf_forward_prepare", "bsf_forward_apply",
            "bsf_backward_workspace_bytes", "bsf_filter_backward", "bsf_batched_workspace_bytes",
            "bsf_filter_batched", "bsf_set_tuning", "bsf_get_tuning", "bsf_read_device_status",
-           "bsf_status_string", "bsf_version", "bsf_filter_varying_noalloc", "bsf_cov_to_steps")
+           "bsf_status_string", "bsf_version", "bsf_filter_varying_noalloc", "bsf_cov_to_steps",
+           "bsf_alg1_workspace_bytes", "bsf_filter_alg1", "bsf_alg2_workspace_bytes", "bsf_filter_alg2")
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -88,13 +89,20 @@ def lib():
                                              ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
         L.bsf_filter_varying_noalloc.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, P, P, P]
         L.bsf_cov_to_steps.argtypes = [cfgp, P, i64, i64, ctypes.c_float, P, P, sz, P]
+        L.bsf_alg1_workspace_bytes.argtypes = [cfgp, i64, i64]
+        L.bsf_alg1_workspace_bytes.restype = sz
+        L.bsf_filter_alg1.argtypes = [cfgp, P, i64, i64, i64, P, P, P, sz, P]
+        L.bsf_alg2_workspace_bytes.argtypes = [cfgp, i64, i64]
+        L.bsf_alg2_workspace_bytes.restype = sz
+        L.bsf_filter_alg2.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, sz, P]
         L.bsf_status_string.argtypes = [i32]
         L.bsf_status_string.restype = ctypes.c_char_p
         L.bsf_version.restype = ctypes.c_char_p
         for name in ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_varying",
                      "bsf_forward_prepare", "bsf_forward_apply",
                      "bsf_filter_backward", "bsf_filter_batched", "bsf_set_tuning",
-                     "bsf_read_device_status", "bsf_filter_varying_noalloc", "bsf_cov_to_steps"):
+                     "bsf_read_device_status", "bsf_filter_varying_noalloc", "bsf_cov_to_steps",
+                     "bsf_filter_alg1", "bsf_filter_alg2"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -316,6 +324,52 @@ def cov_to_steps(cfg: Config, cov: torch.Tensor, sub: float = 0.0, steps: Option
     _check(lib().bsf_cov_to_steps(ctypes.byref(cfg.c()), _ptr(cov), H, W, float(sub), _ptr(steps), ws.ptr(),
                                   ws.nbytes, _stream(cov.device)), "bsf_cov_to_steps")
     return steps
+
+
+def _check_cov(cov, H, W):
+    if cov.dtype != torch.float32 or not cov.is_cuda or not cov.is_contiguous() or tuple(cov.shape) != (3, H, W):
+        raise ValueError("cov must be a contiguous float32 [3][H][W] device tensor")
+
+
+def filter_alg1(cfg: Config, img: torch.Tensor, cov: torch.Tensor, out: Optional[torch.Tensor] = None,
+                ws: Optional[Workspace] = None) -> torch.Tensor:
+    """Alg. 1: isotropic pre-filter of half the condition2 bound, then the
+    space-variant filter of C - sigma^2 I (bsf_filter_alg1)."""
+    _check_image(img)
+    H, W = img.shape
+    _check_cov(cov, H, W)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=img.device)
+    need = lib().bsf_alg1_workspace_bytes(ctypes.byref(cfg.c()), H, W)
+    if need == 0:
+        raise BsfError(E_UNSUPPORTED, "bsf_alg1_workspace_bytes")
+    ws = ws or _workspace(img.device, need)
+    ws.ensure(need)
+    _check(lib().bsf_filter_alg1(ctypes.byref(cfg.c()), _ptr(img), H, W, _pitch(img), _ptr(cov), _ptr(out),
+                                 ws.ptr(), ws.nbytes, _stream(img.device)), "bsf_filter_alg1")
+    return out
+
+
+def filter_alg2(cfg: Config, img: torch.Tensor, cov: torch.Tensor, out: Optional[torch.Tensor] = None,
+                bank: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None) -> torch.Tensor:
+    """Alg. 2: per-pixel choice between the two four-direction box splines by
+    orientation sector (bsf_filter_alg2).  bank (uint8 [H][W]) receives the
+    choice when given."""
+    _check_image(img)
+    H, W = img.shape
+    _check_cov(cov, H, W)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=img.device)
+    if bank is not None and (bank.dtype != torch.uint8 or tuple(bank.shape) != (H, W) or not bank.is_contiguous()):
+        raise ValueError("bank must be a contiguous uint8 [H][W] device tensor")
+    need = lib().bsf_alg2_workspace_bytes(ctypes.byref(cfg.c()), H, W)
+    if need == 0:
+        raise BsfError(E_UNSUPPORTED, "bsf_alg2_workspace_bytes")
+    ws = ws or _workspace(img.device, need)
+    ws.ensure(need)
+    _check(lib().bsf_filter_alg2(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, _pitch(img), _ptr(cov),
+                                 _ptr(out), _ptr(bank), ws.ptr(), ws.nbytes, _stream(img.device)), "bsf_filter_alg2")
+    return out
 
 
 def forward_prepare(cfg: Config, img: torch.Tensor, steps: torch.Tensor, ws: Workspace,

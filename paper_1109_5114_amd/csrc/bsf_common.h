@@ -137,6 +137,10 @@ struct GatherArgs {
     // those (the cluster-box kernels address taps in that fixed frame).
     int32_t canon;
     int32_t canon_plane[4];
+    // nullable: only pixels whose sel entry equals sel_id are written (the
+    // sectors of Alg. 2 filter their pixels from their own running sums)
+    const uint8_t *sel;
+    int32_t sel_id;
 };
 bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st);
 // Arguments of the gather for one image (bsf_api.hip).

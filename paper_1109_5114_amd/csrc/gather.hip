@@ -95,6 +95,11 @@ __device__ __forceinline__ bool pixel_wx(const GatherArgs &a, int64_t bx, int64_
     return x < a.W && y < a.H;
 }
 
+// Pixels of another bank (a.sel non-null and not a.sel_id) are left alone.
+__device__ __forceinline__ bool selected(const GatherArgs &a, int64_t idx) {
+    return !a.sel || a.sel[idx] == a.sel_id;
+}
+
 __device__ __forceinline__ float clamp_step(float s, float max_step) {
     // NaN -> 1 (fmaxf returns the non-NaN operand); keeps every tap in the window
     return fminf(fmaxf(s, 1.0f), max_step);
@@ -270,7 +275,7 @@ __global__ __launch_bounds__(256) void k_gather_int(GatherArgs one, const Gather
     GatherArgs a;
     int64_t bx, by, x, y;
     if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
-    if (!pixel_16x16(a, bx, by, x, y)) return;
+    if (!pixel_16x16(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
     const int M = MT > 0 ? MT : a.M;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
@@ -328,7 +333,7 @@ __global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs one, con
     GatherArgs a;
     int64_t bx, by, x, y;
     if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
-    if (!pixel_16x16(a, bx, by, x, y)) return;
+    if (!pixel_16x16(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
     const int M = a.M;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
@@ -592,7 +597,7 @@ __global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, cons
     GatherArgs a;
     int64_t bx, by, x, y;
     if (!tile_of_block<BATCH>(one, table, prefix, B, WX, 256 / WX, a, bx, by)) return;
-    if (!pixel_wx<WX>(a, bx, by, x, y)) return;
+    if (!pixel_wx<WX>(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
     t2n4_pixel<CONTIG>(a, x, y);
 }
 
@@ -869,7 +874,7 @@ __global__ __launch_bounds__(64 * kFwdWaves, 2) void k_gather_t2n4_box(
     BoxTile t;
     t.x = (int)(bx * kFwdTileW) + fwd_tx(threadIdx.x);
     t.y = (int)(by * kFwdTileH) + fwd_ty(threadIdx.x);
-    const bool active = t.x < a.W && t.y < a.H;
+    const bool active = t.x < a.W && t.y < a.H && selected(a, (int64_t)t.y * a.W + t.x);
     {
         const int64_t HW = a.H * a.W, idx = (int64_t)t.y * a.W + t.x;
 #pragma unroll
@@ -906,7 +911,7 @@ __global__ __launch_bounds__(64 * kFwdWaves, 2) void k_gather_t2n4_box(
     // the pixel's position and phases are formed again here rather than held
     // through the loop
     const int px = t.x_lo + fwd_tx(threadIdx.x), py = t.y_lo + fwd_ty(threadIdx.x);
-    if (px >= a.W || py >= a.H) return;
+    if (px >= a.W || py >= a.H || !selected(a, (int64_t)py * a.W + px)) return;
     const int64_t HW = a.H * a.W, idx = (int64_t)py * a.W + px;
     float ph[4], sk[4];
     double den = 1.0;
@@ -955,7 +960,7 @@ __global__ __launch_bounds__(256) void k_gather_t2n4_fp64(GatherArgs one, const 
     GatherArgs a;
     int64_t bx, by, x, y;
     if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
-    if (!pixel_16x16(a, bx, by, x, y)) return;
+    if (!pixel_16x16(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const double *G = static_cast<const double *>(a.G);
     const int32_t base = (int32_t)((y + a.pad_top) * a.Wp + (x + a.pad_left));
