@@ -62,7 +62,8 @@ def test_alg1_matches_oracle(order):
     rng = np.random.default_rng(410 + order)
     H, W = 84, 101
     img = rng.random((H, W), dtype=np.float32)
-    cov = cov_field(rng, H, W)
+    # moderate elongations and sizes >= 4 px: the isotropic part is sizeable
+    cov = cov_field(rng, H, W, rho_max=2.5, sig=(4.0, 12.0))
     cfg = bsf.Config(order=order, max_step=80.0)
     ws = bsf.Workspace(bsf.lib().bsf_alg1_workspace_bytes(bsf.ctypes.byref(cfg.c()), H, W), DEV)
     out = bsf.filter_alg1(cfg, to_dev(img), to_dev(cov), ws=ws).cpu().numpy()
@@ -72,7 +73,7 @@ def test_alg1_matches_oracle(order):
     _, rs2, _, _ = O.alg1(img[:2, :2], cov[:, :2, :2], order)   # exercise the oracle's own sigma^2 path
     b = np.array([O.condition2_bound(*cov[:, y, x]) for y in range(H) for x in range(W)])
     np.testing.assert_allclose(sigma2, 0.5 * max(b.min(), 0.0), rtol=1e-6)
-    assert sigma2 > 0.5
+    assert sigma2 > 1.0
     s2 = bsf.cov_to_steps(bsf.Config(order=order, max_step=80.0), to_dev(cov), sub=sigma2).cpu().numpy()
     ref, _, _, _ = O.alg1(img, cov, order, sigma2=sigma2, steps2=s2)
     # two fixed-point passes (F of the second reported) and the FP32 rounding

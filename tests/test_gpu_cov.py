@@ -16,13 +16,13 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
 
-def cov_field(rng, H, W, rho_max=None, bank=1):
+def cov_field(rng, H, W, rho_max=None, bank=1, sig=(1.5, 12.0)):
     """Smooth orientation, elongation and size fields -> C11, C12, C22."""
     th = WL.smooth(rng, H, W, 0.0, np.pi)
     rho = WL.smooth(rng, H, W, 1.0, 4.0 if rho_max is None else rho_max)
     if bank == 1 and rho_max is None:
         rho = np.minimum(rho, 0.9 * np.array([[O.elongation_bound(t) for t in row] for row in th]))
-    sig = WL.smooth(rng, H, W, 1.5, 12.0)
+    sig = WL.smooth(rng, H, W, *sig)
     l1, l2 = sig ** 2, sig ** 2 / rho
     c, s = np.cos(th), np.sin(th)
     C11 = l1 * c * c + l2 * s * s
