@@ -194,8 +194,10 @@ bsf_status bsf_filter_varying(const bsf_config *cfg, bsf_dtype dtype, const void
  *   ws must come from a bsf_forward_prepare on the same configuration, image
  *   size and workspace (ws holds F).  The steps may differ from the ones given
  *   to bsf_forward_prepare (one pre-integration serves several step fields, as
- *   the two banks of Alg. 2 do); their fixed-point bound is then rechecked on
- *   the device.  G == NULL reads the running sums from the workspace.
+ *   the two banks of Alg. 2 do); the taps check their range and their
+ *   fixed-point headroom at the stored F (BSF_FLAG_RANGE, BSF_FLAG_OVERFLOW;
+ *   log2_bound keeps the preparing pass's value).  G == NULL reads the
+ *   running sums from the workspace.
  */
 bsf_status bsf_forward_prepare(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H,
                                int64_t W, int64_t pitch, const float *steps, void *G, void *ws,

@@ -148,7 +148,7 @@ bsf_status one_pass(const Plan &p, int src_kind, int32_t frac_bits, const void *
     void *G = ws + kStatusBytes;
     void *aux = ws + kStatusBytes + align_up(p.g_bytes);
     Src src{img, src_kind, p.H, p.W, pitch, p.pad_top, p.pad_left};
-    bsf_status r = run_bound(p, src, steps, src_kind == SRC_F32 ? frac_bits : 0, status, st, false);
+    bsf_status r = run_bound(p, src, steps, src_kind == SRC_F32 ? frac_bits : 0, status, st);
     if (r != BSF_OK) return r;
     r = run_preintegrate(p, src, G, aux, status, st);
     if (r != BSF_OK) return r;

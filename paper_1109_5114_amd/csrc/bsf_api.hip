@@ -144,6 +144,7 @@ GatherArgs gather_args(const Plan &p, const void *G, const float *steps, float *
     a.order = p.order;
     a.tied = p.tied;
     a.n_dirs = p.n_dirs;
+    a.mode = p.mode;
     // Factor order: directions in config order, except that for the tied
     // four-direction order-2 kernel a direction with window offset +1 goes last,
     // so its taps are contiguous.  The result does not depend on the order.
@@ -268,7 +269,7 @@ bsf_status prepare_impl(const bsf_config *cfg, bsf_dtype dtype, const void *img,
     if (H * W == 0) return BSF_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Src src{img, kind, H, W, pitch, p.pad_top, p.pad_left};
-    r = run_bound(p, src, steps, kind == SRC_F32 ? cfg->frac_bits : 0, L.status, st, false);
+    r = run_bound(p, src, steps, kind == SRC_F32 ? cfg->frac_bits : 0, L.status, st);
     if (r != BSF_OK) return r;
     return run_preintegrate(p, src, L.G, L.aux, L.status, st);
 }
@@ -306,10 +307,7 @@ bsf_status bsf_forward_apply(const bsf_config *cfg, bsf_dtype dtype, int64_t H, 
     WsLayout L = ws_layout(p, ws, const_cast<void *>(G));
     if (H * W == 0) return BSF_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    Src none{};
-    none.kind = src_kind_of(dtype);
-    r = run_bound(p, none, steps, 0, L.status, st, true);
-    if (r != BSF_OK) return r;
+    // the taps check these steps themselves (range, and headroom at the stored F)
     GatherArgs a = gather_args(p, L.G, steps, out, out_num, out_den, dout_dsteps, L.status);
     return run_gather(p, a, st);
 }

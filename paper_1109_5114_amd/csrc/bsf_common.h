@@ -129,7 +129,7 @@ struct GatherArgs {
     int64_t *out_den;       // nullable
     const int32_t *status;  // F at status[ST_F_USED]
     float max_step;
-    int M, order, tied, n_dirs;
+    int M, order, tied, n_dirs, mode;
     int32_t off[BSF_MAX_FACTORS];    // window offset (elements) of one lattice step along factor j
     int32_t plane[BSF_MAX_FACTORS];  // step plane of factor j
     // Four directions that are exactly (1,0), (0,1), (1,1), (1,-1) in some
@@ -163,11 +163,11 @@ void make_bound_job(const float *steps, const float *img, int64_t H, int64_t W, 
 bsf_status run_bound_batch(const Plan &p0, int img_kind, int32_t F_request, const void *jobs, const int64_t *prefix,
                            int B, int64_t total_rows, hipStream_t st);
 
-// Bound / range check and fixed-point choice (gather.hip).
-// prepare: range check, bound and choice of F (recheck = false); apply with
-// possibly different steps: range check and bound against the stored F.
+// Bound / range check and fixed-point choice (gather.hip): the range check of
+// the steps, the bound max|f| prod(box lengths) and the choice of F.  The taps
+// repeat the range and headroom checks for the steps they are given.
 bsf_status run_bound(const Plan &p, const Src &src, const float *steps, int32_t F_request, int32_t *status,
-                     hipStream_t st, bool recheck);
+                     hipStream_t st);
 
 // Adjoint (adjoint.hip).  Status words of the backward pass live in the
 // workspace's status block after the forward ones.

@@ -105,6 +105,52 @@ __device__ __forceinline__ float clamp_step(float s, float max_step) {
     return fminf(fmaxf(s, 1.0f), max_step);
 }
 
+// ceil(log2(v)) for v >= 1, from the binary exponent (frexp: v = m 2^e, m in [0.5, 1)).
+__device__ __forceinline__ int ceil_log2(double v) {
+    int e;
+    const double m = __builtin_frexp(v, &e);
+    return m == 0.5 ? e - 1 : e;
+}
+
+// The checks of the preparing pass, repeated by the taps for the steps they
+// are given (they may differ from the ones the window was prepared with):
+// one factor's step s adds to `bad` (NaN, below 1, above max_step, or not an
+// integer in integer mode) and multiplies its box length into `prod`.
+__device__ __forceinline__ void step_check(float s, float max_step, int mode, int reps, bool &bad, double &prod) {
+    if (!(s >= 1.0f) || s > max_step) bad = true;
+    const float sc = clamp_step(s, max_step);
+    double len;
+    if (mode == BSF_STEPS_INT) {
+        if (sc != floorf(sc)) bad = true;
+        len = (double)rintf(sc);
+    } else {
+        len = (double)(2.0f * floorf((sc - 1.0f) * 0.5f) + 3.0f);
+    }
+    for (int r = 0; r < reps; ++r) prod *= len;
+}
+
+// Raises BSF_FLAG_RANGE for a bad step and BSF_FLAG_OVERFLOW when the product
+// of box lengths leaves the tap combination without int64 headroom at the
+// window's F (ef + F + ceil log2 prod > 62).
+__device__ __forceinline__ void report_steps(const GatherArgs &a, bool bad, double prod) {
+    int32_t *status = const_cast<int32_t *>(a.status);
+    if (bad) atomicOr((unsigned *)&status[ST_FLAGS], BSF_FLAG_RANGE);
+    const int ef = a.status[ST_EF];
+    if (a.status[ST_ARITH] == BSF_ARITH_EXACT && ef > -1000 &&
+        ef + a.status[ST_F_USED] + ceil_log2(prod * (1.0 + 0x1p-40)) > 62)
+        atomicOr((unsigned *)&status[ST_FLAGS], BSF_FLAG_OVERFLOW);
+}
+
+// Every plane of a pixel through step_check, then report_steps.
+__device__ __forceinline__ void check_pixel_steps(const GatherArgs &a, int64_t idx) {
+    const int64_t HW = a.H * a.W;
+    const int planes = a.tied ? a.n_dirs : a.M, reps = a.tied ? a.order : 1;
+    bool bad = false;
+    double prod = 1.0;
+    for (int q = 0; q < planes; ++q) step_check(a.steps[q * HW + idx], a.max_step, a.mode, reps, bad, prod);
+    report_steps(a, bad, prod);
+}
+
 __device__ __forceinline__ double ldexp_neg(double v, int F) { return __builtin_ldexp(v, -F); }
 
 // ----------------------------------------------------------------------------
@@ -118,21 +164,12 @@ struct BoundJob {
 };
 
 template <bool BATCH>
-__global__ void k_status_begin(BoundJob one, const BoundJob *__restrict__ jobs, int32_t F_request, int recheck) {
+__global__ void k_status_begin(BoundJob one, const BoundJob *__restrict__ jobs, int32_t F_request) {
     if (threadIdx.x != 0) return;
     int32_t *status = BATCH ? jobs[blockIdx.x].status : one.status;
     status[ST_EP_MAX] = 0;
-    if (!recheck) {
-        status[ST_FABS_BITS] = 0;
-        status[ST_F_REQUEST] = F_request;
-    }
-}
-
-// ceil(log2(v)) for v >= 1, from the binary exponent (frexp: v = m 2^e, m in [0.5, 1)).
-__device__ __forceinline__ int ceil_log2(double v) {
-    int e;
-    const double m = __builtin_frexp(v, &e);
-    return m == 0.5 ? e - 1 : e;
+    status[ST_FABS_BITS] = 0;
+    status[ST_F_REQUEST] = F_request;
 }
 
 // Rows y = first, first + stride, ...; threads stride over columns; a
@@ -161,30 +198,59 @@ __global__ __launch_bounds__(256) void k_bound(BoundJob one, const BoundJob *__r
     unsigned fbits = 0;
     int bad = 0, nonfinite = 0;
     const int64_t H = job.H, W = job.W, HW = H * W;
+    // one factor step: range check, its box length into prod
+    auto factor = [&](float s, double &prod) {
+        if (!(s >= 1.0f) || s > max_step) bad = 1;  // catches NaN
+        const float sc = clamp_step(s, max_step);
+        double len;
+        if (mode == BSF_STEPS_INT) {
+            if (sc != floorf(sc)) bad = 1;
+            len = (double)rintf(sc);
+        } else {
+            len = (double)(2.0f * floorf((sc - 1.0f) * 0.5f) + 3.0f);
+        }
+        for (int r = 0; r < per_plane; ++r) prod *= len;
+    };
+    // products of small integers are exact in FP64 up to 2^53; above that
+    // round the bound up a little so it stays an upper bound
+    auto finish = [&](double prod) { ep_max = max(ep_max, ceil_log2(prod * (1.0 + 0x1p-40))); };
+    auto image = [&](float f_abs) {
+        if (f_abs <= 3.402823466e38f) fbits = max(fbits, __float_as_uint(f_abs));
+        else nonfinite = 1;  // NaN or infinity
+    };
+    // four consecutive pixels per thread and 16-byte loads where rows and
+    // pitches allow them, one pixel at a time otherwise
+    const bool vec = (W % 4 == 0) && (!job.img || job.pitch % 4 == 0);
     for (int64_t y = first; y < H; y += stride) {
-        for (int64_t x = threadIdx.x; x < W; x += blockDim.x) {
-            const int64_t i = y * W + x;
-            double prod = 1.0;
-            for (int q = 0; q < planes; ++q) {
-                const float s = job.steps[q * HW + i];
-                if (!(s >= 1.0f) || s > max_step) bad = 1;  // catches NaN
-                const float sc = clamp_step(s, max_step);
-                double len;
-                if (mode == BSF_STEPS_INT) {
-                    if (sc != floorf(sc)) bad = 1;
-                    len = (double)rintf(sc);
-                } else {
-                    len = (double)(2.0f * floorf((sc - 1.0f) * 0.5f) + 3.0f);
+        if (vec) {
+            for (int64_t x = 4 * (int64_t)threadIdx.x; x < W; x += 4 * (int64_t)blockDim.x) {
+                double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0;
+                for (int q = 0; q < planes; ++q) {
+                    const float4 v = *reinterpret_cast<const float4 *>(job.steps + q * HW + y * W + x);
+                    factor(v.x, p0);
+                    factor(v.y, p1);
+                    factor(v.z, p2);
+                    factor(v.w, p3);
                 }
-                for (int r = 0; r < per_plane; ++r) prod *= len;
+                finish(p0);
+                finish(p1);
+                finish(p2);
+                finish(p3);
+                if (job.img) {
+                    const float4 fv = *reinterpret_cast<const float4 *>(job.img + y * job.pitch + x);
+                    image(fabsf(fv.x));
+                    image(fabsf(fv.y));
+                    image(fabsf(fv.z));
+                    image(fabsf(fv.w));
+                }
             }
-            // products of small integers are exact in FP64 up to 2^53; above
-            // that round the bound up a little so it stays an upper bound
-            ep_max = max(ep_max, ceil_log2(prod * (1.0 + 0x1p-40)));
-            if (job.img) {
-                const float f = fabsf(job.img[y * job.pitch + x]);
-                if (f <= 3.402823466e38f) fbits = max(fbits, __float_as_uint(f));
-                else nonfinite = 1;  // NaN or infinity
+        } else {
+            for (int64_t x = threadIdx.x; x < W; x += blockDim.x) {
+                const int64_t i = y * W + x;
+                double prod = 1.0;
+                for (int q = 0; q < planes; ++q) factor(job.steps[q * HW + i], prod);
+                finish(prod);
+                if (job.img) image(fabsf(job.img[y * job.pitch + x]));
             }
         }
     }
@@ -256,16 +322,6 @@ __global__ void k_choose_F(BoundJob one, const BoundJob *__restrict__ jobs, int 
     status[ST_ARITH] = arith;
 }
 
-// New steps on an existing window: the stored F and image bound must still
-// hold for the new step products.
-__global__ void k_check_F(int32_t *status) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int eP = status[ST_EP_MAX], ef = status[ST_EF], F = status[ST_F_USED];
-    if (status[ST_ARITH] == BSF_ARITH_EXACT && ef > -1000 && ef + F + eP > 62)
-        atomicOr((unsigned *)&status[ST_FLAGS], BSF_FLAG_OVERFLOW);
-    if (ef > -1000 && ef + eP > status[ST_LOG2_BOUND]) status[ST_LOG2_BOUND] = ef + eP;
-}
-
 // ----------------------------------------------------------------------------
 // Integer steps: 2^M signed taps (Table 1 signs (-1)^popcount), exact.
 // ----------------------------------------------------------------------------
@@ -281,16 +337,21 @@ __global__ __launch_bounds__(256) void k_gather_int(GatherArgs one, const Gather
     const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
     int64_t pa[BSF_MAX_FACTORS], pb[BSF_MAX_FACTORS];
     int64_t den = 1;
+    bool bad = false;
+    double prod = 1.0;
 #pragma unroll
     for (int j = 0; j < (MT > 0 ? MT : BSF_MAX_FACTORS); ++j) {
         if (j >= M) break;
-        const float s = clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
+        const float s_raw = a.steps[a.plane[j] * HW + idx];
+        step_check(s_raw, a.max_step, BSF_STEPS_INT, 1, bad, prod);
+        const float s = clamp_step(s_raw, a.max_step);
         const int si = min((int)rintf(s), (int)a.max_step);   // stays inside the window's reach
         const int c = (si - 1) >> 1;
         pa[j] = (int64_t)c * a.off[j];
         pb[j] = (int64_t)(c - si) * a.off[j];
         den *= si;
     }
+    report_steps(a, bad, prod);
     V num = V(0);
     const int n = 1 << M;
     if constexpr (MT > 0) {
@@ -334,6 +395,7 @@ __global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs one, con
     int64_t bx, by, x, y;
     if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
     if (!pixel_16x16(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
+    check_pixel_steps(a, y * a.W + x);
     const int M = a.M;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
@@ -598,6 +660,7 @@ __global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, cons
     int64_t bx, by, x, y;
     if (!tile_of_block<BATCH>(one, table, prefix, B, WX, 256 / WX, a, bx, by)) return;
     if (!pixel_wx<WX>(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
+    check_pixel_steps(a, y * a.W + x);
     t2n4_pixel<CONTIG>(a, x, y);
 }
 
@@ -877,11 +940,16 @@ __global__ __launch_bounds__(64 * kFwdWaves, 2) void k_gather_t2n4_box(
     const bool active = t.x < a.W && t.y < a.H && selected(a, (int64_t)t.y * a.W + t.x);
     {
         const int64_t HW = a.H * a.W, idx = (int64_t)t.y * a.W + t.x;
+        bool bad = false;
+        double prod = 1.0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const float s = active ? clamp_step(a.steps[a.canon_plane[k] * HW + idx], a.max_step) : 1.0f;
+            const float s_raw = active ? a.steps[a.canon_plane[k] * HW + idx] : 1.0f;
+            step_check(s_raw, a.max_step, BSF_STEPS_REAL, 2, bad, prod);
+            const float s = clamp_step(s_raw, a.max_step);
             t.R[k] = (int)floorf((s - 1.0f) * 0.5f);
         }
+        if (active) report_steps(a, bad, prod);
     }
     tile_R_range(t.R, active, t.Rlo, t.Rhi);
     t.x_lo = (int)(bx * kFwdTileW);
@@ -961,6 +1029,7 @@ __global__ __launch_bounds__(256) void k_gather_t2n4_fp64(GatherArgs one, const 
     int64_t bx, by, x, y;
     if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
     if (!pixel_16x16(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
+    check_pixel_steps(a, y * a.W + x);
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const double *G = static_cast<const double *>(a.G);
     const int32_t base = (int32_t)((y + a.pad_top) * a.Wp + (x + a.pad_left));
@@ -1074,20 +1143,17 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
 }  // namespace
 
 bsf_status run_bound(const Plan &p, const Src &src, const float *steps, int32_t F_request, int32_t *status,
-                     hipStream_t st, bool recheck) {
-    BoundJob job{steps, (!recheck && src.kind == SRC_F32) ? static_cast<const float *>(src.img) : nullptr,
-                 p.H, p.W, src.pitch, status};
-    hipLaunchKernelGGL((k_status_begin<false>), dim3(1), dim3(64), 0, st, job, nullptr, F_request, recheck ? 1 : 0);
+                     hipStream_t st) {
+    BoundJob job{steps, src.kind == SRC_F32 ? static_cast<const float *>(src.img) : nullptr, p.H, p.W, src.pitch,
+                 status};
+    hipLaunchKernelGGL((k_status_begin<false>), dim3(1), dim3(64), 0, st, job, nullptr, F_request);
     BSF_HIP_CHECK(hipGetLastError());
     int64_t blocks = p.H < 2048 ? p.H : 2048;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((k_bound<false>), dim3((unsigned)blocks), dim3(256), 0, st, job, nullptr, nullptr, 1, p.planes,
                        p.tied ? p.order : 1, p.mode, p.max_step);
     BSF_HIP_CHECK(hipGetLastError());
-    if (recheck)
-        hipLaunchKernelGGL(k_check_F, dim3(1), dim3(64), 0, st, status);
-    else
-        hipLaunchKernelGGL((k_choose_F<false>), dim3(1), dim3(64), 0, st, job, nullptr, src.kind, p.arith);
+    hipLaunchKernelGGL((k_choose_F<false>), dim3(1), dim3(64), 0, st, job, nullptr, src.kind, p.arith);
     BSF_HIP_CHECK(hipGetLastError());
     return BSF_OK;
 }
@@ -1117,7 +1183,7 @@ bsf_status run_bound_batch(const Plan &p0, int img_kind, int32_t F_request, cons
                            int B, int64_t total_rows, hipStream_t st) {
     const BoundJob *bj = static_cast<const BoundJob *>(jobs);
     BoundJob none{};
-    hipLaunchKernelGGL((k_status_begin<true>), dim3((unsigned)B), dim3(64), 0, st, none, bj, F_request, 0);
+    hipLaunchKernelGGL((k_status_begin<true>), dim3((unsigned)B), dim3(64), 0, st, none, bj, F_request);
     BSF_HIP_CHECK(hipGetLastError());
     if (total_rows > 0) {
         hipLaunchKernelGGL((k_bound<true>), dim3((unsigned)total_rows), dim3(256), 0, st, none, bj, prefix, B,

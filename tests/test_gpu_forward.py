@@ -318,3 +318,32 @@ def test_prepare_then_apply_with_other_steps():
     np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), ref.cpu().numpy().view(np.uint32))
     oref = O.filter(img, DIRS4, 2, True, O.REAL, s2)
     assert_close(out.cpu().numpy(), oref, F, what="prepare/apply")
+
+
+def test_apply_checks_its_own_steps():
+    """forward_apply with steps other than the prepared ones: the taps raise
+    FLAG_RANGE for a bad step and FLAG_OVERFLOW when the new steps' box
+    lengths exceed the headroom of the F chosen for the prepared steps."""
+    note("apply-time checks")
+    shape = (40, 44)
+    rng = np.random.default_rng(32)
+    img = rng.random(shape, dtype=np.float32)
+    small = rand_steps(shape, 4, 1.0, 2.0, 33)            # F chosen for box lengths 3
+    large = rand_steps(shape, 4, 30.0, 31.0, 34)          # lengths 31: 8 * 5 bits more
+    cfg = bsf.Config(order=2, max_step=31.0)
+    dev = torch.device("cuda:0")
+    ti, ts, tl = (torch.from_numpy(a).to(dev) for a in (img, small, large))
+    ws = bsf.Workspace(bsf.plan(cfg, *shape).workspace_bytes, dev)
+    out = torch.empty(shape, dtype=torch.float32, device=dev)
+    bsf.forward_prepare(cfg, ti, ts, ws)
+    bsf.forward_apply(cfg, bsf.F32, ts, ws, out)
+    flags, F, _ = ws.status()
+    assert flags == 0
+    bsf.forward_apply(cfg, bsf.F32, tl, ws, out)
+    flags, _, _ = ws.status(clear=True)
+    assert flags & bsf.FLAG_OVERFLOW and not flags & bsf.FLAG_RANGE
+    bad = small.copy()
+    bad[3, 5, 6] = np.nan
+    bsf.forward_apply(cfg, bsf.F32, torch.from_numpy(bad).to(dev), ws, out)
+    flags, _, _ = ws.status(clear=True)
+    assert flags & bsf.FLAG_RANGE
