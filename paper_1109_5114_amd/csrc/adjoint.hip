@@ -610,7 +610,7 @@ bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *sta
     BSF_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_adj_colsum_scatter, grid, dim3(256), 0, st, a, reinterpret_cast<uint64_t *>(a.Ghat));
     BSF_HIP_CHECK(hipGetLastError());
-    bsf_status r = run_prefix2d(a.Ghat, p.H + 1, p.W + 1, aux, st);
+    bsf_status r = run_prefix2d(a.Ghat, p.H + 1, p.W + 1, aux, status, st);
     if (r != BSF_OK) return r;
     hipLaunchKernelGGL(k_adj_colsum_max, dim3((unsigned)blocks), dim3(256), 0, st,
                        reinterpret_cast<const uint64_t *>(a.Ghat), p.H, p.W, status);

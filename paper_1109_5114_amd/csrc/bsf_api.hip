@@ -375,7 +375,7 @@ bsf_status bsf_filter_backward(const bsf_config *cfg, int64_t H, int64_t W, cons
         }
         r = run_adjoint_scatter(p, a, L.status, L.aux, st);
         if (r != BSF_OK) return r;
-        r = run_preintegrate_transpose(p, L.G, L.aux, st);
+        r = run_preintegrate_transpose(p, L.G, L.aux, L.status, st);
         if (r != BSF_OK) return r;
     }
     return run_adjoint_finish(p, static_cast<const int64_t *>(L.G), L.status, grad_img, gout, dout_dsteps,

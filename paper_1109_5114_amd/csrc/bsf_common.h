@@ -112,10 +112,10 @@ bsf_status run_pass_batch(int arith, int order, int src_kind, int dx, int dy, co
 bsf_status run_preintegrate(const Plan &p, const Src &src, void *G, void *aux, const int32_t *status,
                             hipStream_t st);
 // Reverse (transposed) running sums on the window, last direction first.
-bsf_status run_preintegrate_transpose(const Plan &p, void *G, void *aux, hipStream_t st);
+bsf_status run_preintegrate_transpose(const Plan &p, void *G, void *aux, const int32_t *status, hipStream_t st);
 // Inclusive 2-D prefix sum, in place, of a dense int64 [rows][cols] array
 // (rows <= Hp and cols <= Wp of a plan whose scan_aux_bytes sized aux).
-bsf_status run_prefix2d(int64_t *D, int64_t rows, int64_t cols, void *aux, hipStream_t st);
+bsf_status run_prefix2d(int64_t *D, int64_t rows, int64_t cols, void *aux, const int32_t *status, hipStream_t st);
 
 // Per-pixel taps (gather.hip).
 struct GatherArgs {

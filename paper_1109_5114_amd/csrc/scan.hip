@@ -2,14 +2,17 @@
 // step 2: g(p) = f(p) + g(p - u)), r times per direction, in exact int64
 // (wrapping modulo 2^64) or plain FP64.
 //
-// Rows (dy == 0) use one workgroup per row: 1024-element chunks, a thread-local
-// prefix over 4 contiguous elements, a wavefront prefix (64-bit lane shuffles)
-// and a cross-wave prefix through LDS, with the running carry kept in
-// registers.  All other directions use sheared tiles: 64 lanes follow 64
-// adjacent lines of direction u for TL steps, so every step reads 64 contiguous
-// elements of one row.  A tile's carry comes from the tile before it on the
-// same lines, so the scan runs in three phases (tile aggregates, a per-line scan
-// of aggregates, the final rescan), none of which waits on another workgroup.
+// Rows (dy == 0) use one wavefront per row on a single image and one
+// workgroup per row in a batch (1024-element chunks, a thread-local prefix over
+// 4 contiguous elements, a wavefront prefix and a cross-wave prefix through
+// LDS); the running carry stays in registers.  All other directions use
+// sheared tiles: 64 lanes follow 64 adjacent lines of direction u for TL steps,
+// so every step reads 64 contiguous elements of one row, 16 steps loaded
+// together.  A tile's carry comes from the tile before it on the same lines,
+// so the scan runs in three phases (tile aggregates, a per-line scan of
+// aggregates, the final rescan), none of which waits on another workgroup: a
+// direction has only about (W + H) / 64 groups of lines, so a look-back across
+// the tiles of a line would chain one device-coherent round trip per tile.
 //
 // Every kernel runs either on one image (arguments by value) or on a batch
 // (BATCH: a work list over images, each block looking up its image's job).
@@ -22,6 +25,7 @@ namespace {
 
 constexpr int kRowThreads = 256;
 constexpr int kRowChunk = kRowThreads * 4;
+constexpr int kUnroll = 16;  // steps of a line tile loaded together
 
 template <typename V>
 __device__ __forceinline__ V shfl_up64(V v, int d) {
@@ -170,14 +174,24 @@ __global__ __launch_bounds__(64) void k_line_aggregate(ScanJob one, const ScanJo
     V s[ORDER];
 #pragma unroll
     for (int o = 0; o < ORDER; ++o) s[o] = V(0);
-    for (int64_t t = t0; t < t1; ++t) {
-        int64_t row, col;
-        bool in;
-        line_cell(g, q, c0, t, row, col, in);
-        const V v = in ? load_src<V, SRC>(G, g.Wp, job.src, F, row, col) : V(0);
-        s[0] += v;
+    // kUnroll loads in flight per lane, then their sums
+    for (int64_t tb = t0; tb < t1; tb += kUnroll) {
+        V v[kUnroll];
 #pragma unroll
-        for (int o = 1; o < ORDER; ++o) s[o] += s[o - 1];
+        for (int u = 0; u < kUnroll; ++u) {
+            int64_t row, col;
+            bool in;
+            line_cell(g, q, c0, tb + u, row, col, in);
+            v[u] = (in && tb + u < t1) ? load_src<V, SRC>(G, g.Wp, job.src, F, row, col) : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (tb + u < t1) {
+                s[0] += v[u];
+#pragma unroll
+                for (int o = 1; o < ORDER; ++o) s[o] += s[o - 1];
+            }
+        }
     }
 #pragma unroll
     for (int o = 0; o < ORDER; ++o) aux[(idx * ORDER + o) * 64 + lane] = s[o];
@@ -236,16 +250,132 @@ __global__ __launch_bounds__(64) void k_line_final(ScanJob one, const ScanJob *_
     V s[ORDER];
 #pragma unroll
     for (int o = 0; o < ORDER; ++o) s[o] = aux[(idx * ORDER + o) * 64 + lane];
-    for (int64_t t = t0; t < t1; ++t) {
-        int64_t row, col;
-        bool in;
-        line_cell(g, q, c0, t, row, col, in);
-        const V v = in ? load_src<V, SRC>(G, g.Wp, job.src, F, row, col) : V(0);
-        s[0] += v;
+    for (int64_t tb = t0; tb < t1; tb += kUnroll) {
+        V v[kUnroll];
 #pragma unroll
-        for (int o = 1; o < ORDER; ++o) s[o] += s[o - 1];
-        if (in) G[row * g.Wp + col] = s[ORDER - 1];
+        for (int u = 0; u < kUnroll; ++u) {
+            int64_t row, col;
+            bool in;
+            line_cell(g, q, c0, tb + u, row, col, in);
+            v[u] = (in && tb + u < t1) ? load_src<V, SRC>(G, g.Wp, job.src, F, row, col) : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            int64_t row, col;
+            bool in;
+            line_cell(g, q, c0, tb + u, row, col, in);
+            if (tb + u < t1) {
+                s[0] += v[u];
+#pragma unroll
+                for (int o = 1; o < ORDER; ++o) s[o] += s[o - 1];
+                if (in) G[row * g.Wp + col] = s[ORDER - 1];
+            }
+        }
     }
+}
+
+// ----------------------------------------------------------------------------
+// Single-image row passes: one wavefront per row, segments of 128 elements
+// with lane l holding elements 2l and 2l + 1; per order level the pair is
+// summed, a wavefront prefix of the pair sums gives each lane its offset, and
+// the carry moves to the next segment in registers.  Four segments are
+// scanned together (their prefixes do not depend on the carry) and the next
+// four are loaded before they are.
+// ----------------------------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ V wave_incl_scan(V x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const V t = shfl_up64(x, d);
+        if (lane >= d) x += t;
+    }
+    return x;
+}
+
+template <typename V, int ORDER, int SRC>
+__global__ __launch_bounds__(256) void k_row_scan_wave(ScanJob job) {
+    constexpr int kSeg = 4;  // segments per step: their wavefront prefixes are independent
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= job.Hp) return;  // the whole wavefront
+    V *__restrict__ G = static_cast<V *>(job.G);
+    const int64_t Wp = job.Wp;
+    const int dir = job.dir;
+    const int F = (SRC == SRC_F32) ? job.status[ST_F_USED] : 0;
+    auto col_of = [&](int64_t e) { return dir > 0 ? e : Wp - 1 - e; };
+    auto load_step = [&](int64_t step, V x[2 * kSeg]) {
+#pragma unroll
+        for (int k = 0; k < kSeg; ++k) {
+            const int64_t e0 = (step * kSeg + k) * 128 + 2 * lane;
+            x[2 * k] = e0 < Wp ? load_src<V, SRC>(G, Wp, job.src, F, row, col_of(e0)) : V(0);
+            x[2 * k + 1] = e0 + 1 < Wp ? load_src<V, SRC>(G, Wp, job.src, F, row, col_of(e0 + 1)) : V(0);
+        }
+    };
+    V carry[ORDER];
+#pragma unroll
+    for (int o = 0; o < ORDER; ++o) carry[o] = V(0);
+    const int64_t nstep = (Wp + 128 * kSeg - 1) / (128 * kSeg);
+    V a[2 * kSeg], b[2 * kSeg];
+    load_step(0, a);
+    for (int64_t step = 0; step < nstep; ++step) {
+        if (step + 1 < nstep) load_step(step + 1, b);
+#pragma unroll
+        for (int o = 0; o < ORDER; ++o) {
+            V incl[kSeg];
+#pragma unroll
+            for (int k = 0; k < kSeg; ++k) {
+                a[2 * k + 1] += a[2 * k];
+                incl[k] = wave_incl_scan<V>(a[2 * k + 1]);
+            }
+#pragma unroll
+            for (int k = 0; k < kSeg; ++k) {
+                const V add = incl[k] - a[2 * k + 1] + carry[o];
+                a[2 * k] += add;
+                a[2 * k + 1] += add;
+                carry[o] += __shfl(incl[k], 63, 64);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kSeg; ++k) {
+            const int64_t e0 = (step * kSeg + k) * 128 + 2 * lane;
+            if (e0 < Wp) G[row * Wp + col_of(e0)] = a[2 * k];
+            if (e0 + 1 < Wp) G[row * Wp + col_of(e0 + 1)] = a[2 * k + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * kSeg; ++k) a[k] = b[k];
+    }
+}
+
+template <typename V, int ORDER, int SRC>
+bsf_status pass_single_sweep(int dx, int dy, const ScanJob &job, void *aux, hipStream_t st) {
+    (void)dx;
+    (void)aux;
+    hipLaunchKernelGGL((k_row_scan_wave<V, ORDER, SRC>), dim3((unsigned)((job.Hp + 3) / 4)), dim3(256), 0, st, job);
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
+}
+
+template <typename V, int ORDER>
+bsf_status sweep_dispatch_src(int src_kind, int dx, int dy, const ScanJob &job, void *aux, hipStream_t st) {
+    switch (src_kind) {
+    case SRC_WINDOW: return pass_single_sweep<V, ORDER, SRC_WINDOW>(dx, dy, job, aux, st);
+    case SRC_F32: return pass_single_sweep<V, ORDER, SRC_F32>(dx, dy, job, aux, st);
+    case SRC_U8: return pass_single_sweep<V, ORDER, SRC_U8>(dx, dy, job, aux, st);
+    case SRC_U16: return pass_single_sweep<V, ORDER, SRC_U16>(dx, dy, job, aux, st);
+    }
+    return BSF_E_INVALID;
+}
+
+template <typename V>
+bsf_status sweep_dispatch(int order, int src_kind, int dx, int dy, const ScanJob &job, void *aux, hipStream_t st) {
+    switch (order) {
+    case 1: return sweep_dispatch_src<V, 1>(src_kind, dx, dy, job, aux, st);
+    case 2: return sweep_dispatch_src<V, 2>(src_kind, dx, dy, job, aux, st);
+    case 3: return sweep_dispatch_src<V, 3>(src_kind, dx, dy, job, aux, st);
+    case 4: return sweep_dispatch_src<V, 4>(src_kind, dx, dy, job, aux, st);
+    }
+    return BSF_E_UNSUPPORTED;
 }
 
 // Launch one pass: a by-value job (jobs == nullptr) or a batch.
@@ -324,14 +454,12 @@ bsf_status pass_single(int arith, int order, int dx, int dy, int64_t Hp, int64_t
     job.Hp = Hp;
     job.Wp = Wp;
     job.dir = dx > 0 ? 1 : -1;
-    int64_t items, groups = 0;
     if (dy == 0) {
-        items = Hp;
-    } else {
-        job.g = line_geom(dx, dy, Hp, Wp, tuning().line_tl);
-        items = job.g.ay * job.g.n_chunks * job.g.n_groups;
-        groups = job.g.ay * job.g.n_groups;
+        if (arith == BSF_ARITH_FP64) return sweep_dispatch<double>(order, src.kind, dx, dy, job, aux, st);
+        return sweep_dispatch<int64_t>(order, src.kind, dx, dy, job, aux, st);
     }
+    job.g = line_geom(dx, dy, Hp, Wp, tuning().line_tl);
+    const int64_t items = job.g.ay * job.g.n_chunks * job.g.n_groups, groups = job.g.ay * job.g.n_groups;
     if (arith == BSF_ARITH_FP64)
         return pass_dispatch<double>(order, src.kind, dy, job, nullptr, nullptr, items, nullptr, groups, 1, st);
     return pass_dispatch<int64_t>(order, src.kind, dy, job, nullptr, nullptr, items, nullptr, groups, 1, st);
@@ -381,23 +509,23 @@ bsf_status run_preintegrate(const Plan &p, const Src &src, void *G, void *aux, c
     return BSF_OK;
 }
 
-bsf_status run_preintegrate_transpose(const Plan &p, void *G, void *aux, hipStream_t st) {
+bsf_status run_preintegrate_transpose(const Plan &p, void *G, void *aux, const int32_t *status, hipStream_t st) {
     Src s{};
     s.kind = SRC_WINDOW;
     for (int k = p.n_dirs - 1; k >= 0; --k) {
         bsf_status r =
-            pass_single(BSF_ARITH_EXACT, p.order, -p.dx[k], -p.dy[k], p.Hp, p.Wp, s, G, aux, nullptr, st);
+            pass_single(BSF_ARITH_EXACT, p.order, -p.dx[k], -p.dy[k], p.Hp, p.Wp, s, G, aux, status, st);
         if (r != BSF_OK) return r;
     }
     return BSF_OK;
 }
 
-bsf_status run_prefix2d(int64_t *D, int64_t rows, int64_t cols, void *aux, hipStream_t st) {
+bsf_status run_prefix2d(int64_t *D, int64_t rows, int64_t cols, void *aux, const int32_t *status, hipStream_t st) {
     Src s{};
     s.kind = SRC_WINDOW;
-    bsf_status r = pass_single(BSF_ARITH_EXACT, 1, 1, 0, rows, cols, s, D, aux, nullptr, st);
+    bsf_status r = pass_single(BSF_ARITH_EXACT, 1, 1, 0, rows, cols, s, D, aux, status, st);
     if (r != BSF_OK) return r;
-    return pass_single(BSF_ARITH_EXACT, 1, 0, 1, rows, cols, s, D, aux, nullptr, st);
+    return pass_single(BSF_ARITH_EXACT, 1, 0, 1, rows, cols, s, D, aux, status, st);
 }
 
 bsf_status run_pass_batch(int arith, int order, int src_kind, int dx, int dy, const ScanJob *jobs,
