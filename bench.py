@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--int-size", type=int, default=2048, help="integer-step uint8 workload side (0: skip)")
     ap.add_argument("--int-steps", type=int, default=20)
+    ap.add_argument("--diff-images", type=int, default=16, help="images of the differentiation workload (0: skip)")
+    ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, one device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -96,8 +98,9 @@ def main():
     tuning = None
     if not args.no_tune:
         t = time.time()
-        tuning = tuner.tune(cfg, H, W, dev)
-        log("tuned in %.1f s: gather_wx %d line_tl %d" % (time.time() - t, tuning["gather_wx"], tuning["line_tl"]))
+        tuning = tuner.tune(cfg, H, W, dev, img=img, steps=steps)
+        log("tuned in %.1f s: gather_wx %d line_tl %d box_h %d" % (time.time() - t, tuning["gather_wx"],
+                                                                   tuning["line_tl"], tuning["box_h"]))
     geo = bsf.plan(cfg, H, W)
     ws = bsf.Workspace(geo.workspace_bytes, dev)
     out = torch.empty((H, W), dtype=torch.float32, device=dev)
@@ -122,11 +125,26 @@ def main():
         ev[k][2].record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - w0) / K * 1e3
-    prep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    apply_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
-    step_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
+    # medians over the timed steps (HIP events on the launch stream)
+    prep_ms = float(np.median([e[0].elapsed_time(e[1]) for e in ev]))
+    apply_ms = float(np.median([e[1].elapsed_time(e[2]) for e in ev]))
+    step_ms = float(np.median([e[0].elapsed_time(e[2]) for e in ev]))
     flags, F, log2b = ws.status()
     mpx = H * W / (step_ms / 1e3) / 1e6
+    # algorithmic HBM bytes of the forward as built (what each pass must move
+    # at least once): the range/F pass reads the four FP32 step planes and the
+    # image; the first running sum reads the image and writes the window; each
+    # sheared pass reads its input twice (aggregates, rescan) and writes it
+    # once; the taps read the window once, the steps, and write the output
+    win = geo.win_h * geo.win_w
+    px = H * W
+    forward_bytes = px * (16 + 4) + (px * 4 + win * 8) + 3 * win * 24 + (win * 8 + px * (16 + 4))
+    # backward with the step derivative: the forward writes d out / d steps
+    # (16 B/px); the adjoint reads g (twice: its range and the scatter), writes
+    # the window once, runs four transposed passes (row 16, sheared 24 B per
+    # element) and reads the window, g and d out / d steps to write both gradients
+    backward_bytes = px * 16 + px * 8 + win * 8 + win * (16 + 3 * 24) + (win * 8 + px * (4 + 16 + 4 + 16))
+    minimum_bytes = 40 * px
     log("step %.3f ms (prepare %.3f, apply %.3f, wall %.3f), F=%d flags=%d" % (step_ms, prep_ms, apply_ms, wall,
                                                                           F, flags))
 
@@ -200,11 +218,51 @@ def main():
                              want_img=False)
         ggs = gs.cpu().numpy().reshape(4, -1)[:, sub].T
         gerr = float(np.max(np.abs(ggs - rgs)) / max(np.abs(rgs).max(), 1e-30))
-        t_fa = float(np.mean(fwd_ms) + np.mean(bwd_ms))
+        t_fa = float(np.median(fwd_ms) + np.median(bwd_ms))
+        fa_bytes = forward_bytes + backward_bytes
         fa = {"ms_per_step": t_fa, "value": H * W / (t_fa / 1e3) / 1e6, "unit": "Mpixels/s",
-              "forward_with_derivative_ms": float(np.mean(fwd_ms)), "backward_ms": float(np.mean(bwd_ms)),
+              "forward_with_derivative_ms": float(np.median(fwd_ms)), "backward_ms": float(np.median(bwd_ms)),
+              "hbm_gbs": fa_bytes / (t_fa / 1e3) / 1e9, "hbm_frac": fa_bytes / (t_fa / 1e3) / 1e9 / HBM_PEAK_GBS,
+              "algorithmic_bytes": fa_bytes,
               "steps": args.adjoint_steps, "grad_steps_max_rel_err_vs_oracle": gerr}
-        log("fwd+adjoint %.3f ms (fwd %.3f, bwd %.3f)" % (t_fa, np.mean(fwd_ms), np.mean(bwd_ms)))
+        log("fwd+adjoint %.3f ms (fwd %.3f, bwd %.3f)" % (t_fa, np.median(fwd_ms), np.median(bwd_ms)))
+
+    # ---- differentiation workload: 16 images of 1024^2, forward with the step
+    # derivative and the adjoint for every image
+    diff = None
+    if args.diff_images > 0:
+        d5 = WL.workload5(B=args.diff_images)
+        cfg5 = bsf.Config(dirs=d5["dirs"], order=2, tied=True, mode=bsf.STEPS_REAL, max_step=d5["max_step"])
+        H5, W5 = d5["imgs"][0].shape
+        ws5 = bsf.Workspace(bsf.plan(cfg5, H5, W5).workspace_bytes, dev)
+        wsb5 = bsf.Workspace(bsf.backward_workspace_bytes(cfg5, H5, W5), dev)
+        imgs5 = [torch.from_numpy(a).to(dev) for a in d5["imgs"]]
+        steps5 = [torch.from_numpy(a).to(dev) for a in d5["steps"]]
+        gouts5 = [torch.from_numpy(a).to(dev) for a in d5["gout"]]
+        out5, ds5 = torch.empty((H5, W5), dtype=torch.float32, device=dev), torch.empty_like(steps5[0])
+        gi5, gs5 = torch.empty_like(out5), torch.empty_like(steps5[0])
+
+        def diff_step():
+            for im, st, g in zip(imgs5, steps5, gouts5):
+                bsf.forward_prepare(cfg5, im, st, ws5)
+                bsf.forward_apply(cfg5, bsf.F32, st, ws5, out5, dsteps=ds5)
+                bsf.filter_backward(cfg5, st, g, dsteps=ds5, ws=wsb5, grad_img=gi5, grad_steps=gs5)
+
+        diff_step()
+        torch.cuda.synchronize()
+        t5 = []
+        for _ in range(args.diff_steps):
+            e0.record(stream)
+            diff_step()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t5.append(e0.elapsed_time(e1))
+        ms5 = float(np.median(t5))
+        px5 = len(imgs5) * H5 * W5
+        diff = {"workload": d5["name"], "images": len(imgs5), "ms_per_step": ms5,
+                "value": px5 / (ms5 / 1e3) / 1e6, "unit": "Mpixels/s", "steps": args.diff_steps}
+        log("differentiation %d x %dx%d fwd+adjoint: %.3f ms" % (len(imgs5), H5, W5, ms5))
+        del imgs5, steps5, gouts5, ws5, wsb5
 
     # ---- integer steps on a uint8 image: exact int64 numerator and prod s
     integer = None
@@ -233,8 +291,8 @@ def main():
             bsf.forward_apply(cfg3, bsf.U8, steps3, ws3, out3, num=num3, den=den3)
             ev3[k][2].record(stream)
         torch.cuda.synchronize()
-        p3 = float(np.mean([e[0].elapsed_time(e[1]) for e in ev3]))
-        a3 = float(np.mean([e[1].elapsed_time(e[2]) for e in ev3]))
+        p3 = float(np.median([e[0].elapsed_time(e[1]) for e in ev3]))
+        a3 = float(np.median([e[1].elapsed_time(e[2]) for e in ev3]))
         pix3 = rng.integers(0, H3 * W3, 64)
         _, rnum, rden = O.filter(d3["img"], d3["dirs"], 1, True, O.INT, d3["steps"], pix=pix3, want_int=True)
         exact = bool(np.array_equal(num3.cpu().numpy().reshape(-1)[pix3], rnum)
@@ -265,6 +323,9 @@ def main():
         tuning4 = None if args.no_tune else tuner.tune(cfg4, side, side, dev)
         imgs4 = [torch.from_numpy(it["img"]).to(dev) for it in d4["items"]]
         steps4 = [torch.from_numpy(it["steps"]).to(dev) for it in d4["items"]]
+        if tuning4 is not None:
+            # the batch's own gather tile, timed on its own images and steps
+            tuning4["box_h"] = tuner.tune_batch(cfg4, imgs4, steps4)["box_h"]
         batch = bsf.Batch(cfg4, imgs4, steps4)
         batch.run(use_graph=True)                       # records the graph
         torch.cuda.synchronize()
@@ -297,7 +358,7 @@ def main():
                    "images": len(px), "pixels": int(sum(px)), "graph": True, "steps": args.batch_steps,
                    "per_image_calls_ms": loop_ms, "frac_bits": bF, "device_flags": bflags,
                    "max_rel_err_vs_oracle": berr,
-                   "tuning": None if tuning4 is None else {k: tuning4[k] for k in ("gather_wx", "line_tl")},
+                   "tuning": None if tuning4 is None else {k: tuning4[k] for k in ("gather_wx", "line_tl", "box_h")},
                    "workload": d4["name"]}
         log("batched %d images %.1f Mpx: %.3f ms (per-image calls %.3f ms)" % (len(px), sum(px) / 1e6, b_ms,
                                                                                 loop_ms))
@@ -361,7 +422,13 @@ def main():
         "fwd_adjoint": fa,
         "batched": batched,
         "integer_steps": integer,
-        "tuning": None if tuning is None else {k: tuning[k] for k in ("gather_wx", "line_tl")},
+        "hbm": {"gbs": forward_bytes / (step_ms / 1e3) / 1e9,
+                "frac": forward_bytes / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                "algorithmic_bytes": forward_bytes, "minimum_bytes": minimum_bytes,
+                "minimum_gbs": minimum_bytes / (step_ms / 1e3) / 1e9,
+                "peak_gbs": HBM_PEAK_GBS},
+        "differentiation": diff,
+        "tuning": None if tuning is None else {k: tuning[k] for k in ("gather_wx", "line_tl", "box_h")},
     }
     print(json.dumps(res))
 

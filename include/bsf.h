@@ -338,6 +338,17 @@ bsf_status bsf_set_tuning(int32_t gather_wx, int32_t line_tl);
 void bsf_get_tuning(int32_t *gather_wx, int32_t *line_tl);
 
 /*
+ * Tile of the tied order-2 gather along (1,0), (0,1), (1,1), (1,-1) (the
+ * kernel that stages the running sums in LDS boxes): 8 (16 x 8 pixels, boxes
+ * of up to 38 rows; the default) or 4 (16 x 4 pixels, boxes of up to 18 rows).
+ * Tiles whose step range needs taller boxes read their taps from the window
+ * directly, so the faster choice depends on how fast the steps vary; results
+ * are the same.  Same rules as bsf_set_tuning; BSF_E_INVALID for other values.
+ */
+bsf_status bsf_set_box_tile(int32_t tile_h);
+int32_t bsf_get_box_tile(void);
+
+/*
  * Synchronises `stream`, then copies the status word from the workspace
  * (host outputs): *flags gets BSF_FLAG_* bits, *F_used the fixed-point bits of
  * the last forward call, *log2_bound the bound ceil(log2 max|f| + log2 max prod)

@@ -56,7 +56,8 @@ EXPORTS = ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_var
            "bsf_backward_workspace_bytes", "bsf_filter_backward", "bsf_batched_workspace_bytes",
            "bsf_filter_batched", "bsf_set_tuning", "bsf_get_tuning", "bsf_read_device_status",
            "bsf_status_string", "bsf_version", "bsf_filter_varying_noalloc", "bsf_cov_to_steps",
-           "bsf_alg1_workspace_bytes", "bsf_filter_alg1", "bsf_alg2_workspace_bytes", "bsf_filter_alg2")
+           "bsf_alg1_workspace_bytes", "bsf_filter_alg1", "bsf_alg2_workspace_bytes", "bsf_filter_alg2",
+           "bsf_set_box_tile", "bsf_get_box_tile")
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -95,6 +96,9 @@ def lib():
         L.bsf_alg2_workspace_bytes.argtypes = [cfgp, i64, i64]
         L.bsf_alg2_workspace_bytes.restype = sz
         L.bsf_filter_alg2.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, sz, P]
+        L.bsf_set_box_tile.argtypes = [i32]
+        L.bsf_get_box_tile.argtypes = []
+        L.bsf_get_box_tile.restype = i32
         L.bsf_status_string.argtypes = [i32]
         L.bsf_status_string.restype = ctypes.c_char_p
         L.bsf_version.restype = ctypes.c_char_p
@@ -102,7 +106,7 @@ def lib():
                      "bsf_forward_prepare", "bsf_forward_apply",
                      "bsf_filter_backward", "bsf_filter_batched", "bsf_set_tuning",
                      "bsf_read_device_status", "bsf_filter_varying_noalloc", "bsf_cov_to_steps",
-                     "bsf_filter_alg1", "bsf_filter_alg2"):
+                     "bsf_filter_alg1", "bsf_filter_alg2", "bsf_set_box_tile"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -434,6 +438,16 @@ def set_tuning(gather_wx: int, line_tl: int):
     """Launch shapes of the tied order-2 gather and the sheared running sums
     (process-wide; results do not depend on them)."""
     _check(lib().bsf_set_tuning(int(gather_wx), int(line_tl)), "bsf_set_tuning")
+
+
+def set_box_tile(tile_h: int):
+    """Tile height (4 or 8) of the tied order-2 cluster-box gather (process-wide;
+    results do not depend on it)."""
+    _check(lib().bsf_set_box_tile(int(tile_h)), "bsf_set_box_tile")
+
+
+def get_box_tile() -> int:
+    return int(lib().bsf_get_box_tile())
 
 
 def get_tuning() -> Tuple[int, int]:

@@ -116,7 +116,7 @@ bsf_status make_plan(const bsf_config *cfg, int64_t H, int64_t W, Plan *p) {
 
 namespace bsf {
 
-Tuning g_tuning{16, 64};
+Tuning g_tuning{16, 64, 8};
 const Tuning &tuning() { return g_tuning; }
 
 size_t ws_bytes_for(const Plan &p, bool g_internal) {
@@ -406,6 +406,14 @@ bsf_status bsf_set_tuning(int32_t gather_wx, int32_t line_tl) {
     g_tuning.line_tl = line_tl;
     return BSF_OK;
 }
+
+bsf_status bsf_set_box_tile(int32_t tile_h) {
+    if (tile_h != 4 && tile_h != 8) return BSF_E_INVALID;
+    g_tuning.box_h = tile_h;
+    return BSF_OK;
+}
+
+int32_t bsf_get_box_tile(void) { return g_tuning.box_h; }
 
 void bsf_get_tuning(int32_t *gather_wx, int32_t *line_tl) {
     if (gather_wx) *gather_wx = g_tuning.gather_wx;

@@ -54,6 +54,7 @@ bsf_status make_plan(const bsf_config *cfg, int64_t H, int64_t W, Plan *p);
 struct Tuning {
     int gather_wx;   // width in pixels of the wavefront block of the tied order-2 gather (8, 16, 32, 64)
     int line_tl;     // steps per line tile of the sheared scans (power of two, 16 .. 4096)
+    int box_h;       // tile height of the cluster-box tied order-2 gather (4 or 8)
 };
 const Tuning &tuning();
 

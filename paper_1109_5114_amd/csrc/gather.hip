@@ -695,19 +695,26 @@ __device__ __forceinline__ int fresh_lane_id() {
     return id;
 }
 
-// Tile of the forward cluster-box kernel: kFwdTileW columns by kFwdTileH rows
-// of pixels, one wavefront per 16 x 4 block of them, and the LDS box rows it
-// stages.
+// Tiles of the forward cluster-box kernel: 16 columns by TH rows of pixels, one
+// wavefront per 16 x 4 block of them, and the LDS box rows each stages: 16 x 8
+// tiles of two wavefronts with 38-row boxes (four workgroups per CU in 158 KB of
+// LDS), or 16 x 4 tiles of one wavefront with 18-row boxes (eight workgroups per
+// CU in 150 KB).  Narrower boxes waste less of every copy, but tiles whose step
+// range needs more rows fall back to direct window reads, so the best shape
+// depends on how fast the step field varies (the tuner times both).
 constexpr int kFwdTileW = 16;
-constexpr int kFwdTileH = 8;
-constexpr int kFwdWaves = (kFwdTileW / 16) * (kFwdTileH / 4);
-constexpr int kFwdRows = 38;
-constexpr int kFwdElems = cbox::kPitch * kFwdRows;
-static_assert(kFwdTileW % 16 == 0 && kFwdTileH % 4 == 0 && kFwdTileW + 64 * (kFwdTileH - 1) < 1024 &&
-                  kFwdRows % 2 == 0, "tile shape");
+template <int TH>
+struct FwdShape {
+    static_assert(TH == 4 || TH == 8, "tile heights");
+    static constexpr int H = TH;
+    static constexpr int Waves = TH / 4;
+    static constexpr int Rows = TH == 8 ? 38 : 18;
+    static constexpr int Elems = cbox::kPitch * Rows;
+    static_assert(kFwdTileW + 64 * (TH - 1) < 1024 && Rows % 2 == 0, "tile shape");
+};
 // Position of thread i's pixel in the tile.
-__device__ __forceinline__ int fwd_tx(int i) { return 16 * ((i >> 6) % (kFwdTileW / 16)) + (i & 15); }
-__device__ __forceinline__ int fwd_ty(int i) { return 4 * ((i >> 6) / (kFwdTileW / 16)) + ((i >> 4) & 3); }
+__device__ __forceinline__ int fwd_tx(int i) { return i & 15; }
+__device__ __forceinline__ int fwd_ty(int i) { return 4 * (i >> 6) + ((i >> 4) & 3); }
 
 // Patch row (Y + 2) of the lowest sub-tap a row tuple of combination C reads.
 __host__ __device__ constexpr int tuple_max_row(int C, int r0, int r1, int r2, int r3) {
@@ -793,11 +800,12 @@ __device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, co
 // Start copying box b of the window into the LDS buffer dst (rows of kPitch
 // elements) with LDS-direct loads: one instruction moves two box rows as 64
 // aligned pairs of elements (lane l: row l / 32, elements 2 (l % 32) and the
-// next), wavefront w taking the row pairs w, w + kFwdWaves, ...; lanes whose pair
+// next), wavefront w of WAVES taking the row pairs w, w + WAVES, ...; lanes whose pair
 // lies right of the box idle, as do the second-row lanes of a last, unpaired
 // row.  The loop runs on wavefront-uniform values only: a pair's window row
 // and LDS row advance by scalar adds.  Completion is waited for (vmcnt)
 // before the barrier that publishes the box.
+template <int WAVES>
 __device__ __forceinline__ void box_stage_async(const GatherArgs &a, uint64_t *__restrict__ dst,
                                                 const cbox::Box &b, int w) {
     static_assert(cbox::kPitch == 64, "two box rows per 64-lane copy");
@@ -810,11 +818,11 @@ __device__ __forceinline__ void box_stage_async(const GatherArgs &a, uint64_t *_
     const char *__restrict__ row =
         reinterpret_cast<const char *>(static_cast<const uint64_t *>(a.G) +
                                        ((int64_t)(b.oy + a.pad_top + 2 * w) * Wp + (b.ox + a.pad_left)));
-    const int64_t row_step = 2 * kFwdWaves * Wp * 8;             // kFwdWaves pairs of window rows, bytes
+    const int64_t row_step = 2 * WAVES * Wp * 8;             // WAVES pairs of window rows, bytes
     uint64_t *l = dst + 2 * w * cbox::kPitch;
     const int full = b.bh >> 1;                                  // pairs with both rows in the box
     int pr = w;
-    for (; pr < full; pr += kFwdWaves, row += row_step, l += 2 * kFwdWaves * cbox::kPitch)
+    for (; pr < full; pr += WAVES, row += row_step, l += 2 * WAVES * cbox::kPitch)
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(row + lane_off),
                                          (__attribute__((address_space(3))) void *)l, 16, 0, 0);
     if ((b.bh & 1) && pr == full && !upper)
@@ -837,7 +845,7 @@ struct BoxTile {
 // Combination I reads buffer I % 2 while combination I + 1 is copied into the
 // other one; one barrier per combination publishes the next box and frees the
 // current one.
-template <int I>
+template <int I, class S>
 __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__restrict__ s_box, bool active,
                                             const BoxTile &t, uint64_t J[81]) {
     constexpr int C = cbox::order_at(I);
@@ -845,7 +853,7 @@ __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__res
     if constexpr (I + 1 < cbox::kCombos) {
         constexpr int Cn = cbox::order_at(I + 1);
         const cbox::Box bn = cbox::box_of<Cn>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left);
-        box_stage_async(a, s_box + ((I + 1) & 1) * kFwdElems, bn, t.wave);
+        box_stage_async<S::Waves>(a, s_box + ((I + 1) & 1) * S::Elems, bn, t.wave);
     }
     if constexpr (I == cbox::kEven) {
 #pragma unroll
@@ -856,14 +864,14 @@ __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__res
         // afresh from the lane number: neither the state, its decoded fields
         // nor its address stay live across combinations
         const uint32_t st = t.state[64 * t.wave + fresh_lane_id()];
-        int base = (I & 1) * kFwdElems + cbox::packed_base<C>(st, t.x_lo, t.y_lo, t.Rlo, b);
+        int base = (I & 1) * S::Elems + cbox::packed_base<C>(st, t.x_lo, t.y_lo, t.Rlo, b);
         int base_hi = base + 4 * cbox::kPitch;
         asm("" : "+v"(base), "+v"(base_hi));
         box_fwd_combo<C>(s_box + base, s_box + base_hi, J);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if constexpr (I + 1 < cbox::kCombos) box_fwd_all<I + 1>(a, s_box, active, t, J);
+    if constexpr (I + 1 < cbox::kCombos) box_fwd_all<I + 1, S>(a, s_box, active, t, J);
 }
 
 __device__ __forceinline__ double contract81(const double Jd[81], const double w0[3], const double w1[3],
@@ -890,8 +898,9 @@ __device__ __forceinline__ double contract81(const double Jd[81], const double w
 }
 
 // Tile-wide min / max of R per direction over the active pixels.
+template <int WAVES>
 __device__ __forceinline__ void tile_R_range(const int R[4], bool active, int Rlo[4], int Rhi[4]) {
-    __shared__ int s_red[kFwdWaves][8];
+    __shared__ int s_red[WAVES][8];
     int lo[4], hi[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -917,7 +926,7 @@ __device__ __forceinline__ void tile_R_range(const int R[4], bool active, int Rl
     for (int k = 0; k < 4; ++k) {
         int l = s_red[0][k], h = s_red[0][4 + k];
 #pragma unroll
-        for (int v = 1; v < kFwdWaves; ++v) {
+        for (int v = 1; v < WAVES; ++v) {
             l = min(l, s_red[v][k]);
             h = max(h, s_red[v][4 + k]);
         }
@@ -926,17 +935,18 @@ __device__ __forceinline__ void tile_R_range(const int R[4], bool active, int Rl
     }
 }
 
-template <bool BATCH>
-__global__ __launch_bounds__(64 * kFwdWaves, 2) void k_gather_t2n4_box(
+template <bool BATCH, int TH>
+__global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box(
     GatherArgs one, const GatherArgs *__restrict__ table, const int64_t *__restrict__ prefix, int B) {
-    __shared__ uint64_t s_box[2 * kFwdElems];
-    __shared__ uint32_t s_state[64 * kFwdWaves];
+    using S = FwdShape<TH>;
+    __shared__ uint64_t s_box[2 * S::Elems];
+    __shared__ uint32_t s_state[64 * S::Waves];
     GatherArgs a;
     int64_t bx, by;
-    if (!tile_of_block_xcd<BATCH>(one, table, prefix, B, kFwdTileW, kFwdTileH, a, bx, by)) return;
+    if (!tile_of_block_xcd<BATCH>(one, table, prefix, B, kFwdTileW, TH, a, bx, by)) return;
     BoxTile t;
     t.x = (int)(bx * kFwdTileW) + fwd_tx(threadIdx.x);
-    t.y = (int)(by * kFwdTileH) + fwd_ty(threadIdx.x);
+    t.y = (int)(by * TH) + fwd_ty(threadIdx.x);
     const bool active = t.x < a.W && t.y < a.H && selected(a, (int64_t)t.y * a.W + t.x);
     {
         const int64_t HW = a.H * a.W, idx = (int64_t)t.y * a.W + t.x;
@@ -951,16 +961,16 @@ __global__ __launch_bounds__(64 * kFwdWaves, 2) void k_gather_t2n4_box(
         }
         if (active) report_steps(a, bad, prod);
     }
-    tile_R_range(t.R, active, t.Rlo, t.Rhi);
+    tile_R_range<S::Waves>(t.R, active, t.Rlo, t.Rhi);
     t.x_lo = (int)(bx * kFwdTileW);
-    t.y_lo = (int)(by * kFwdTileH);
+    t.y_lo = (int)(by * TH);
     t.x_hi = (int)min((int64_t)t.x_lo + kFwdTileW - 1, a.W - 1);
-    t.y_hi = (int)min((int64_t)t.y_lo + kFwdTileH - 1, a.H - 1);
+    t.y_hi = (int)min((int64_t)t.y_lo + TH - 1, a.H - 1);
     t.pad_left = (int)a.pad_left;
     t.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     s_state[threadIdx.x] = cbox::pack_state(fwd_tx(threadIdx.x), fwd_ty(threadIdx.x), t.R, t.Rlo, active);
     t.state = s_state;
-    if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, kFwdRows)) {
+    if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, S::Rows)) {
         if (active) {
             if (a.off[6] == 1) t2n4_pixel<true>(a, t.x, t.y);
             else t2n4_pixel<false>(a, t.x, t.y);
@@ -970,12 +980,11 @@ __global__ __launch_bounds__(64 * kFwdWaves, 2) void k_gather_t2n4_box(
     uint64_t J[81];
 #pragma unroll
     for (int q = 0; q < 81; ++q) J[q] = 0;
-    box_stage_async(a, s_box,
-                    cbox::box_of<cbox::order_at(0)>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left),
-                    t.wave);
+    box_stage_async<S::Waves>(
+        a, s_box, cbox::box_of<cbox::order_at(0)>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left), t.wave);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    box_fwd_all<0>(a, s_box, active, t, J);
+    box_fwd_all<0, S>(a, s_box, active, t, J);
     // the pixel's position and phases are formed again here rather than held
     // through the loop
     const int px = t.x_lo + fwd_tx(threadIdx.x), py = t.y_lo + fwd_ty(threadIdx.x);
@@ -1085,7 +1094,7 @@ GatherShape gather_shape(const Plan &p, const GatherArgs &a) {
         } else if (a.canon) {
             s.kind = 4;
             s.tile_w = kFwdTileW;
-            s.tile_h = kFwdTileH;
+            s.tile_h = tuning().box_h;
         } else {
             s.kind = 2;
             const bool contig = a.off[6] == 1;
@@ -1111,7 +1120,7 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
     } else {
         grid = dim3((unsigned)((p.W + s.tile_w - 1) / s.tile_w), (unsigned)((p.H + s.tile_h - 1) / s.tile_h));
     }
-    dim3 block(s.kind == 4 ? 64 * kFwdWaves : 256);
+    dim3 block(s.kind == 4 ? 16 * s.tile_h : 256);
     const bool fp64 = p.arith == BSF_ARITH_FP64;
     if (s.kind == 0) {
         if (p.M == 4) {
@@ -1124,7 +1133,8 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
     } else if (s.kind == 3) {
         hipLaunchKernelGGL((k_gather_t2n4_fp64<BATCH>), grid, block, 0, st, one, table, prefix, B);
     } else if (s.kind == 4) {
-        hipLaunchKernelGGL((k_gather_t2n4_box<BATCH>), grid, block, 0, st, one, table, prefix, B);
+        if (s.tile_h == 4) hipLaunchKernelGGL((k_gather_t2n4_box<BATCH, 4>), grid, block, 0, st, one, table, prefix, B);
+        else hipLaunchKernelGGL((k_gather_t2n4_box<BATCH, 8>), grid, block, 0, st, one, table, prefix, B);
     } else if (s.kind == 2) {
         const bool contig = one.off[6] == 1;
         if (!contig) hipLaunchKernelGGL((k_gather_t2n4<false, 2, 16, BATCH>), grid, block, 0, st, one, table, prefix, B);
@@ -1165,7 +1175,8 @@ bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st) {
 
 int gather_variant(const Plan &p, const GatherArgs &a) {
     const GatherShape s = gather_shape(p, a);
-    return s.kind | (s.tile_w << 4) | ((a.off[6] == 1) << 12) | ((p.M == 4) << 13) | (p.arith << 14);
+    return s.kind | (s.tile_w << 4) | ((a.off[6] == 1) << 12) | ((p.M == 4) << 13) | (p.arith << 14) |
+           (s.tile_h << 16);
 }
 
 int64_t gather_tiles(const Plan &p, const GatherArgs &a) {

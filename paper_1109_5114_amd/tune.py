@@ -1,17 +1,25 @@
-"""Autotuner for the launch shapes of libbsf (bsf_set_tuning).
+"""Autotuner for the launch shapes of libbsf (bsf_set_tuning, bsf_set_box_tile).
 
-Two shapes are free and do not change any result:
+Three shapes are free and do not change any result:
   * line_tl   -- steps per tile of the sheared running sums; it trades the
                  number of tiles (parallelism, carry traffic) against the
                  length of each tile's serial walk;
   * gather_wx -- width of one wavefront's pixel block in the tied order-2
-                 four-direction gather; it sets which rows of the running-sum
-                 window a wavefront's taps touch together (cache reuse).
+                 four-direction gather for direction sets other than
+                 (1,0), (0,1), (1,1), (1,-1); it sets which rows of the
+                 running-sum window a wavefront's taps touch together;
+  * box_h     -- tile height (4 or 8) of the cluster-box gather used for
+                 (1,0), (0,1), (1,1), (1,-1): short tiles copy less of the window
+                 per pixel but fall back to direct reads where the steps vary
+                 quickly, so the choice depends on the step field.
 The scans and the gather are separate launches, so each shape is timed on its
 own stage: the running sums through bsf_preintegrate for every tile length,
-then the per-pixel taps through bsf_forward_apply for every block width, on a
-synthetic image of the workload's size and step range.  Each candidate's time
-is the median of a few runs bracketed by HIP events on the launch stream.
+then the per-pixel taps through bsf_forward_apply for every gather shape, on
+the caller's image and steps when given (the step field decides the gather),
+otherwise on a synthetic image with smooth steps over the workload's range.
+A batch is tuned as a whole (tune_batch): bsf_filter_batched is timed with
+each box height.  Each candidate's time is the median of a few runs bracketed
+by HIP events on the launch stream.
 
 Winners are kept in a JSON file keyed by device, configuration and size class
 (log2 of the pixel count), so a process that has tuned once for a workload
@@ -24,11 +32,12 @@ from typing import Dict, Optional, Sequence, Tuple
 
 import torch
 
-from . import (ARITH_EXACT, STEPS_INT, Config, Workspace, forward_apply, forward_prepare, get_tuning, plan,
-               preintegrate, set_tuning)
+from . import (ARITH_EXACT, STEPS_INT, Batch, Config, Workspace, forward_apply, forward_prepare, get_box_tile,
+               get_tuning, plan, preintegrate, set_box_tile, set_tuning)
 
 LINE_TL = (32, 64, 128, 256, 512)
 GATHER_WX = (8, 16, 32, 64)
+BOX_H = (8, 4)
 
 
 def _median_ms(fn, reps: int, stream) -> float:
@@ -45,12 +54,23 @@ def _median_ms(fn, reps: int, stream) -> float:
 
 
 def _synthetic(cfg: Config, H: int, W: int, device, seed: int = 0) -> Tuple[torch.Tensor, torch.Tensor]:
+    """A uniform image and, per step plane, a smooth field over [1, max_step]
+    (a few low-frequency cosines), as step fields from covariance maps are."""
     g = torch.Generator(device="cpu").manual_seed(seed)
     img = torch.rand((H, W), generator=g, dtype=torch.float32)
-    if cfg.mode == STEPS_INT:
-        steps = torch.randint(1, int(cfg.max_step) + 1, (cfg.planes, H, W), generator=g).to(torch.float32)
-    else:
-        steps = 1.0 + (cfg.max_step - 1.0) * torch.rand((cfg.planes, H, W), generator=g, dtype=torch.float32)
+    yy = torch.arange(H, dtype=torch.float64)[:, None] / max(H, 1)
+    xx = torch.arange(W, dtype=torch.float64)[None, :] / max(W, 1)
+    planes = []
+    for _ in range(cfg.planes):
+        f = torch.zeros((H, W), dtype=torch.float64)
+        for _ in range(6):
+            kx, ky = torch.randint(-3, 4, (2,), generator=g).tolist()
+            ph = float(torch.rand((1,), generator=g)) * 2 * math.pi
+            f += torch.cos(2 * math.pi * (kx * xx + ky * yy) + ph)
+        f = (f - f.min()) / max(float(f.max() - f.min()), 1e-12)
+        s = 1.0 + (cfg.max_step - 1.0) * f
+        planes.append(torch.round(s) if cfg.mode == STEPS_INT else s)
+    steps = torch.stack(planes).to(torch.float32)
     return img.to(device), steps.to(device)
 
 
@@ -69,20 +89,25 @@ def _load(path: Optional[str]) -> Dict[str, Dict[str, int]]:
 
 
 def tune(cfg: Config, H: int, W: int, device="cuda", reps: int = 3, cache: Optional[str] = None,
-         line_tl: Sequence[int] = LINE_TL, gather_wx: Sequence[int] = GATHER_WX, verbose: bool = False):
-    """Pick (gather_wx, line_tl) for images of about H x W under cfg, set it
-    process-wide and return {"gather_wx", "line_tl", "timings"}."""
+         line_tl: Sequence[int] = LINE_TL, gather_wx: Sequence[int] = GATHER_WX, box_h: Sequence[int] = BOX_H,
+         img: Optional[torch.Tensor] = None, steps: Optional[torch.Tensor] = None, verbose: bool = False):
+    """Pick (gather_wx, line_tl, box_h) for images of about H x W under cfg
+    (timed on img and steps when given), set them process-wide and return
+    {"gather_wx", "line_tl", "box_h", "timings"}."""
     device = torch.device(device)
     key = _key(cfg, H, W, device)
     table = _load(cache)
     if key in table:
         best = table[key]
         set_tuning(best["gather_wx"], best["line_tl"])
+        set_box_tile(best.get("box_h", get_box_tile()))
         return dict(best, cached=True)
-    old = get_tuning()
-    img, steps = _synthetic(cfg, H, W, device)
+    old, old_h = get_tuning(), get_box_tile()
+    if img is None or steps is None:
+        img, steps = _synthetic(cfg, H, W, device)
+    H, W = img.shape
     stream = torch.cuda.current_stream(device)
-    timings = {"line_tl": {}, "gather_wx": {}}
+    timings = {"line_tl": {}, "gather": {}}
     try:
         # running sums: every tile length, the gather's shape left as it is
         for tl in line_tl:
@@ -94,28 +119,35 @@ def tune(cfg: Config, H: int, W: int, device="cuda", reps: int = 3, cache: Optio
             timings["line_tl"][tl] = ms
             del ws
         best_tl = min(timings["line_tl"], key=timings["line_tl"].get)
-        # taps: every block width on one prepared window
+        # taps: every gather shape on one prepared window
         set_tuning(old[0], best_tl)
         g = plan(cfg, H, W)
         ws = Workspace(g.workspace_bytes, device)
         forward_prepare(cfg, img, steps, ws)
         out = torch.empty((H, W), dtype=torch.float32, device=device)
-        # the block width only shapes the tied order-2 kernel for direction sets
-        # other than (1,0), (0,1), (1,1), (1,-1); those use the cluster-box kernel
         canonical = sorted(map(tuple, cfg.dirs)) == sorted(((1, 0), (0, 1), (1, 1), (1, -1)))
-        uses_wx = cfg.mode != STEPS_INT and cfg.order == 2 and cfg.tied and cfg.n_dirs == 4 \
-            and cfg.arith == ARITH_EXACT and not canonical
-        for wx in (gather_wx if uses_wx else (old[0],)):
+        t2n4 = cfg.mode != STEPS_INT and cfg.order == 2 and cfg.tied and cfg.n_dirs == 4 \
+            and cfg.arith == ARITH_EXACT
+        if t2n4 and canonical:
+            shapes = [(old[0], h) for h in box_h]
+        elif t2n4:
+            shapes = [(wx, old_h) for wx in gather_wx]
+        else:
+            shapes = [(old[0], old_h)]
+        for wx, h in shapes:
             set_tuning(wx, best_tl)
+            set_box_tile(h)
             forward_apply(cfg, 3, steps, ws, out)    # warm-up
             ms = _median_ms(lambda: forward_apply(cfg, 3, steps, ws, out), reps, stream)
-            timings["gather_wx"][wx] = ms
-        best_wx = min(timings["gather_wx"], key=timings["gather_wx"].get)
+            timings["gather"]["%d,%d" % (wx, h)] = ms
+        best_wx, best_h = min(shapes, key=lambda sh: timings["gather"]["%d,%d" % sh])
     except Exception:
         set_tuning(*old)
+        set_box_tile(old_h)
         raise
     set_tuning(best_wx, best_tl)
-    best = {"gather_wx": int(best_wx), "line_tl": int(best_tl)}
+    set_box_tile(best_h)
+    best = {"gather_wx": int(best_wx), "line_tl": int(best_tl), "box_h": int(best_h)}
     if verbose:
         print("tune %s -> %s %s" % (key, best, timings), flush=True)
     if cache:
@@ -126,3 +158,31 @@ def tune(cfg: Config, H: int, W: int, device="cuda", reps: int = 3, cache: Optio
             json.dump(table, fh, indent=1, sort_keys=True)
         os.replace(tmp, cache)
     return dict(best, timings=timings, cached=False)
+
+
+def tune_batch(cfg: Config, imgs: Sequence[torch.Tensor], steps: Sequence[torch.Tensor], reps: int = 3,
+               box_h: Sequence[int] = BOX_H, verbose: bool = False):
+    """Pick the cluster-box tile height for a batch by timing the batched call
+    (without graph capture) on the caller's images and steps with each; sets it
+    process-wide and returns {"box_h", "timings"}."""
+    if not imgs:
+        return {"box_h": get_box_tile(), "timings": {}}
+    device = imgs[0].device
+    stream = torch.cuda.current_stream(device)
+    old_h = get_box_tile()
+    timings = {}
+    try:
+        for h in box_h:
+            set_box_tile(h)
+            b = Batch(cfg, imgs, steps)
+            b.run(use_graph=False)                   # warm-up
+            timings[h] = _median_ms(lambda: b.run(use_graph=False), reps, stream)
+            del b
+    except Exception:
+        set_box_tile(old_h)
+        raise
+    best = min(timings, key=timings.get)
+    set_box_tile(best)
+    if verbose:
+        print("tune_batch -> box_h %d %s" % (best, timings), flush=True)
+    return {"box_h": int(best), "timings": timings}

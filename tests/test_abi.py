@@ -243,3 +243,16 @@ def test_plan_accepts_upward_directions_anywhere(dirs):
     assert g.pad_left == sum(lo * dx for dx, dy in dirs)
     assert g.pad_top == sum(lo * dy if dy > 0 else hi * -dy for dx, dy in dirs)
     assert g.pad_bottom == sum(hi * dy if dy > 0 else lo * -dy for dx, dy in dirs)
+
+
+def test_box_tile_setter_validates():
+    h0 = bsf.get_box_tile()
+    assert h0 == 8
+    try:
+        bsf.set_box_tile(4)
+        assert bsf.get_box_tile() == 4
+        for bad in (0, 2, 6, 16):
+            assert bsf.lib().bsf_set_box_tile(bad) == bsf.E_INVALID
+        assert bsf.get_box_tile() == 4
+    finally:
+        bsf.set_box_tile(h0)

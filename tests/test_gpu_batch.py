@@ -133,23 +133,25 @@ def test_isotropic_batch_matches_oracle():
         assert_close(out.reshape(-1)[pix], ref, F, what="image %d" % b)
 
 
-@pytest.mark.parametrize("wx,tl", [(8, 16), (32, 128), (64, 1024)])
-def test_tuning_does_not_change_results(wx, tl):
-    note("tuning", wx, tl)
+@pytest.mark.parametrize("wx,tl,bh", [(8, 16, 4), (32, 128, 8), (64, 1024, 4)])
+def test_tuning_does_not_change_results(wx, tl, bh):
+    note("tuning", wx, tl, bh)
     cfg = bsf.Config(order=2, max_step=14.0)
     imgs, steps = make_batch([(97, 211)], 4, 1.0, 14.0, 81)
     ti, ts = to_dev(imgs)[0], to_dev(steps)[0]
     ref = bsf.filter_varying(cfg, ti, ts).cpu().numpy()
     G_ref = bsf.preintegrate(cfg, ti, F=24).cpu().numpy()
-    old = bsf.get_tuning()
+    old, old_h = bsf.get_tuning(), bsf.get_box_tile()
     try:
         bsf.set_tuning(wx, tl)
+        bsf.set_box_tile(bh)
         got = bsf.filter_varying(cfg, ti, ts).cpu().numpy()
         G = bsf.preintegrate(cfg, ti, F=24).cpu().numpy()
         batch = bsf.Batch(cfg, [ti], [ts])
         got_b = batch.run(use_graph=False)[0].cpu().numpy()
     finally:
         bsf.set_tuning(*old)
+        bsf.set_box_tile(old_h)
     np.testing.assert_array_equal(G, G_ref)
     np.testing.assert_array_equal(got, ref)
     np.testing.assert_array_equal(got_b, ref)
@@ -177,3 +179,26 @@ def test_full_isotropic_batch_matches_oracle():
         pix = np.unique(np.concatenate([rng.integers(0, H * W, 12), [0, W - 1, (H - 1) * W, H * W - 1]]))
         ref = O.filter(im, d["dirs"], 2, True, O.REAL, st, pix=pix)
         assert_close(out.reshape(-1)[pix], ref, F, what="image %d" % b)
+
+
+@pytest.mark.parametrize("bh", [4, 8])
+def test_box_tile_shapes_match_oracle(bh):
+    """Both cluster-box tile heights against the oracle on a frame whose steps
+    vary slowly in some places and quickly in others (tiles that fit the boxes
+    and tiles that fall back)."""
+    note("box tile", bh)
+    rng = np.random.default_rng(85)
+    H, W = 140, 150
+    img = rng.random((H, W), dtype=np.float32)
+    st = np.stack([WL.smooth(rng, H, W, 1.0, 30.0) for _ in range(4)]).astype(np.float32)
+    st[:, 60:80, :] = rng.uniform(1.0, 30.0, size=(4, 20, W)).astype(np.float32)   # a band of rough steps
+    cfg = bsf.Config(order=2, max_step=30.0)
+    old_h = bsf.get_box_tile()
+    try:
+        bsf.set_box_tile(bh)
+        out = bsf.filter_varying(cfg, to_dev([img])[0], to_dev([st])[0]).cpu().numpy()
+    finally:
+        bsf.set_box_tile(old_h)
+    ref = O.filter(img, bsf.DIRS4, 2, True, O.REAL, st)
+    F = expected_F(cfg, img, st)
+    assert_close(out, ref, F, what="box tile %d" % bh)
