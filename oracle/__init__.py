@@ -52,6 +52,9 @@ def lib():
         L.bsfo_condition2_bound.argtypes = [d, d, d]
         L.bsfo_condition2_bound.restype = d
         L.bsfo_bank_of.argtypes = [d]
+        L.bsfo_unit_box_spline.argtypes = [P, d, d]
+        L.bsfo_unit_box_spline.restype = d
+        L.bsfo_alg3.argtypes = [P, l, l, P, P, l, P, P]
         _lib = L
     return _lib
 
@@ -323,3 +326,51 @@ def alg2(img, cov, order=2, steps=None):
             st = np.where(np.isfinite(st), np.maximum(st, 1.0), 1.0).astype(np.float32)
             out[pix] = filter(img, dirs, order, True, REAL, st, pix=pix)
     return out.reshape(H, W), banks
+
+
+# ----------------------------------------------------------------------------- Alg. 3
+
+BANK2_PAPER = ((2, 1), (1, 2), (-1, 2), (-2, 1))  # Table 1's a_1 .. a_4, as the paper orients them
+
+
+def _upper(dirs):
+    """Each direction turned into the upper half-plane (dy > 0, or dy == 0 and
+    dx > 0): the filter is the centred box spline, whatever the signs."""
+    out = []
+    for dx, dy in dirs:
+        if dy < 0 or (dy == 0 and dx < 0):
+            dx, dy = -dx, -dy
+        out.append((int(dx), int(dy)))
+    return out
+
+
+def unit_box_spline(dirs, x, y):
+    """beta_b of eq. interpolation: the box spline of one lattice step along
+    each of the four directions, unit mass, at (x, y)."""
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1))
+    return lib().bsfo_unit_box_spline(_p(d), float(x), float(y))
+
+
+def alg3(img, dirs, steps, pix=None):
+    """Alg. 3 (running sums, eq. interpolation, Table 1 taps, eq. shifts) on a
+    float image [H][W] with steps [4][H][W] (lattice steps along each
+    direction, >= 1).  Returns float64 [H][W] (or the values at pix)."""
+    img = np.ascontiguousarray(img, dtype=np.float32)
+    H, W = img.shape
+    st = np.ascontiguousarray(steps, dtype=np.float32)
+    d = np.ascontiguousarray(np.asarray(_upper(dirs), dtype=np.int32).reshape(-1))
+    if pix is None:
+        out = np.zeros(H * W)
+        r = lib().bsfo_alg3(_p(img), H, W, _p(d), _p(st), 0, None, _p(out))
+        out = out.reshape(H, W)
+    else:
+        pix = np.ascontiguousarray(pix, dtype=np.int64)
+        out = np.zeros(len(pix))
+        r = lib().bsfo_alg3(_p(img), H, W, _p(d), _p(st), len(pix), _p(pix), _p(out))
+    if r == -1:
+        raise ValueError("directions")
+    if r == -2:
+        raise ValueError("a step below 1")
+    if r < 0:
+        raise MemoryError("alg3")
+    return out

@@ -730,6 +730,211 @@ int bsfo_cov_to_steps_field(const int *dirs, int order, long n, const float *cov
     return bad ? -1 : 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Alg. 3 as printed, with eq. interpolation: the running sum g of the image  */
+/* along four directions is read between lattice points as                    */
+/*     F(p) = sum_m g(m) beta_b(p - m),                                        */
+/* beta_b the box spline of one lattice step along each of the directions (the */
+/* paper's beta'_b with scales sqrt(5), the length of those lattice vectors),  */
+/* and the 2^4 signed taps of Table 1 sit at the real positions                */
+/*     p = x + sum_k ((s_k - 1)/2 - eps_k s_k) u_k                             */
+/* (the first is x + tau of eq. shifts), with w = 1 / prod s_k.               */
+/* ------------------------------------------------------------------------- */
+
+/* Area of the intersection of two convex quadrilaterals, each given by its
+ * corners in counter-clockwise order: the corners of each inside the other
+ * and the crossings of their edges, ordered by angle about their mean, then
+ * the shoelace formula. */
+static int inside_convex(const double Q[4][2], double x, double y)
+{
+    for (int i = 0; i < 4; i++) {
+        const double *a = Q[i], *b = Q[(i + 1) % 4];
+        double cr = (b[0] - a[0]) * (y - a[1]) - (b[1] - a[1]) * (x - a[0]);
+        if (cr < -1e-12) return 0;
+    }
+    return 1;
+}
+
+static double area_of_intersection(const double P[4][2], const double Q[4][2])
+{
+    double pts[32][2];
+    int n = 0;
+    for (int i = 0; i < 4; i++) {
+        if (inside_convex(Q, P[i][0], P[i][1])) { pts[n][0] = P[i][0]; pts[n][1] = P[i][1]; n++; }
+        if (inside_convex(P, Q[i][0], Q[i][1])) { pts[n][0] = Q[i][0]; pts[n][1] = Q[i][1]; n++; }
+    }
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) {
+            const double *a = P[i], *b = P[(i + 1) % 4], *c = Q[j], *d = Q[(j + 1) % 4];
+            double rx = b[0] - a[0], ry = b[1] - a[1], sx = d[0] - c[0], sy = d[1] - c[1];
+            double den = rx * sy - ry * sx;
+            if (fabs(den) < 1e-15) continue;
+            double t = ((c[0] - a[0]) * sy - (c[1] - a[1]) * sx) / den;
+            double u = ((c[0] - a[0]) * ry - (c[1] - a[1]) * rx) / den;
+            if (t < 0 || t > 1 || u < 0 || u > 1) continue;
+            pts[n][0] = a[0] + t * rx;
+            pts[n][1] = a[1] + t * ry;
+            n++;
+        }
+    if (n < 3) return 0.0;
+    double cx = 0, cy = 0;
+    for (int i = 0; i < n; i++) { cx += pts[i][0]; cy += pts[i][1]; }
+    cx /= n;
+    cy /= n;
+    double ang[32];
+    for (int i = 0; i < n; i++) ang[i] = atan2(pts[i][1] - cy, pts[i][0] - cx);
+    for (int i = 1; i < n; i++)  /* insertion sort by angle */
+        for (int j = i; j > 0 && ang[j] < ang[j - 1]; j--) {
+            double ta = ang[j]; ang[j] = ang[j - 1]; ang[j - 1] = ta;
+            double tx = pts[j][0], ty = pts[j][1];
+            pts[j][0] = pts[j - 1][0]; pts[j][1] = pts[j - 1][1];
+            pts[j - 1][0] = tx; pts[j - 1][1] = ty;
+        }
+    double a2 = 0.0;
+    for (int i = 0; i < n; i++) {
+        int k = (i + 1) % n;
+        a2 += pts[i][0] * pts[k][1] - pts[k][0] * pts[i][1];
+    }
+    return 0.5 * fabs(a2);
+}
+
+/* The parallelogram {a u + b v : |a|, |b| <= 1/2} centred at (cx, cy), corners
+ * counter-clockwise. */
+static void parallelogram(const int *u, const int *v, double cx, double cy, double Q[4][2])
+{
+    const double s[4][2] = {{-0.5, -0.5}, {0.5, -0.5}, {0.5, 0.5}, {-0.5, 0.5}};
+    for (int i = 0; i < 4; i++) {
+        Q[i][0] = cx + s[i][0] * u[0] + s[i][1] * v[0];
+        Q[i][1] = cy + s[i][0] * u[1] + s[i][1] * v[1];
+    }
+    if ((double)u[0] * v[1] - (double)u[1] * v[0] < 0) {  /* make it counter-clockwise */
+        for (int i = 0; i < 2; i++) {
+            double tx = Q[i][0], ty = Q[i][1];
+            Q[i][0] = Q[3 - i][0]; Q[i][1] = Q[3 - i][1];
+            Q[3 - i][0] = tx; Q[3 - i][1] = ty;
+        }
+    }
+}
+
+/* beta_b at (x, y) for the four integer directions dirs: the box splines of
+ * the pairs (u0, u1) and (u2, u3) are their parallelograms with unit mass, so
+ * beta_b(p) = |P01 ^ (p - P23)| / (|det(u0, u1)| |det(u2, u3)|) (P23 is
+ * symmetric about 0, so p - P23 = p + P23). */
+double bsfo_unit_box_spline(const int *dirs, double x, double y)
+{
+    double P[4][2], Q[4][2];
+    parallelogram(dirs + 0, dirs + 2, 0.0, 0.0, P);
+    parallelogram(dirs + 4, dirs + 6, x, y, Q);
+    double d01 = fabs((double)dirs[0] * dirs[3] - (double)dirs[1] * dirs[2]);
+    double d23 = fabs((double)dirs[4] * dirs[7] - (double)dirs[5] * dirs[6]);
+    return area_of_intersection(P, Q) / (d01 * d23);
+}
+
+/* Alg. 3 at pixels pix (or at every pixel) of a float image [H][W] (FP64 out).
+ *
+ * dirs: four canonical integer directions (dy > 0, or dy == 0 and dx > 0);
+ * steps [4][H][W]: the length s_k >= 1 of direction k's box at each pixel, in
+ * lattice steps along u_k (the paper's a_k / sqrt(5) for its directions).
+ *
+ * Step 2, the recursions g <- g + g(. - u_k) one direction after another, runs
+ * over a rectangle of lattice points holding every point the interpolation
+ * reads together with every point those depend on: all directions point into
+ * y >= 0, so a point (x, y) depends only on points (x', y') with y' <= y and
+ * x' <= x + c (y - y'), c = max ceil(-dx/dy) over directions with dx < 0, and
+ * the sums vanish left of x = -c y.  No pass is cut short, so g is the running
+ * sum of the zero-extended image, accumulated in long double.
+ *
+ * Step 3 takes the 16 taps of Table 1 in the order of dirs (bit k of the tap
+ * index moves the tap by -s_k u_k, the sign is (-1)^(number of set bits)), the
+ * shift of eq. shifts, generalised to tau = (1/2) sum_k (s_k - 1) u_k (the
+ * paper's -3 in tau_2 is -(1/2) sum_k u_k for its directions: each running sum
+ * read through a unit box is displaced by half a step), and w = 1 / prod s_k
+ * (the sqrt(5) weights of the recursions and of a_k cancel).  Returns 0, -1
+ * for directions outside the accepted half-plane, -2 for a step below 1. */
+int bsfo_alg3(const float *img, long H, long W, const int *dirs, const float *steps, long n_pix, const long *pix,
+              double *out)
+{
+    const long HW = H * W, count = pix ? n_pix : HW;
+    long c = 0;
+    double ex = 0, ey = 0;
+    for (int k = 0; k < 4; k++) {
+        int dx = dirs[2 * k], dy = dirs[2 * k + 1];
+        if (dy < 0 || (dy == 0 && dx <= 0)) return -1;
+        if (dx < 0) {
+            long slope = (-dx + dy - 1) / dy; /* ceil(-dx / dy) */
+            if (slope > c) c = slope;
+        }
+        ex += 0.5 * abs(dx);
+        ey += 0.5 * dy;
+    }
+    /* the lattice points the interpolation reads: a bounding box over all taps */
+    long qx_lo = 0, qx_hi = W - 1, qy_hi = H - 1;
+    for (long n = 0; n < count; n++) {
+        long pidx = pix ? pix[n] : n, x = pidx % W, y = pidx / W;
+        for (int k = 0; k < 4; k++)
+            if (!(steps[k * HW + pidx] >= 1.0f)) return -2;
+        for (int e = 0; e < 16; e++) {
+            double qx = x, qy = y;
+            for (int k = 0; k < 4; k++) {
+                double s = steps[k * HW + pidx], t = (s - 1.0) / 2.0 - ((e >> k) & 1) * s;
+                qx += t * dirs[2 * k];
+                qy += t * dirs[2 * k + 1];
+            }
+            long xl = (long)floor(qx - ex) - 1, xh = (long)ceil(qx + ex) + 1, yh = (long)ceil(qy + ey) + 1;
+            if (xl < qx_lo) qx_lo = xl;
+            if (xh > qx_hi) qx_hi = xh;
+            if (yh > qy_hi) qy_hi = yh;
+        }
+    }
+    const long y1 = qy_hi, x0 = (qx_lo < -c * y1 - 1 ? qx_lo : -c * y1 - 1), x1 = qx_hi + c * y1;
+    const long RW = x1 - x0 + 1, RH = y1 + 1;
+    long double *g = calloc((size_t)RW * RH, sizeof(long double));
+    if (!g) return -3;
+    for (long y = 0; y < H; y++)
+        for (long x = 0; x < W; x++) g[y * RW + (x - x0)] = img[y * W + x];
+    /* step 2: g_k(m) = g_{k-1}(m) + g_k(m - u_k), rows ascending, columns ascending */
+    for (int k = 0; k < 4; k++) {
+        const long dx = dirs[2 * k], dy = dirs[2 * k + 1];
+        for (long y = 0; y < RH; y++)
+            for (long x = x0; x <= x1; x++) {
+                long px = x - dx, py = y - dy;
+                if (px < x0 || px > x1 || py < 0) continue; /* zero there */
+                g[y * RW + (x - x0)] += g[py * RW + (px - x0)];
+            }
+    }
+    /* step 3 */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long n = 0; n < count; n++) {
+        long pidx = pix ? pix[n] : n, x = pidx % W, y = pidx / W;
+        double s[4], den = 1.0;
+        for (int k = 0; k < 4; k++) {
+            s[k] = steps[k * HW + pidx];
+            den *= s[k];
+        }
+        long double acc = 0.0L;
+        for (int e = 0; e < 16; e++) {
+            double qx = x, qy = y;
+            for (int k = 0; k < 4; k++) {
+                double t = (s[k] - 1.0) / 2.0 - ((e >> k) & 1) * s[k];
+                qx += t * dirs[2 * k];
+                qy += t * dirs[2 * k + 1];
+            }
+            /* eq. interpolation: F(q) = sum over |m - q| <= reach of g(m) beta_b(q - m) */
+            long double F = 0.0L;
+            for (long my = (long)ceil(qy - ey); my <= (long)floor(qy + ey); my++)
+                for (long mx = (long)ceil(qx - ex); mx <= (long)floor(qx + ex); mx++) {
+                    if (my < 0 || mx < x0) continue; /* g vanishes there */
+                    double wgt = bsfo_unit_box_spline(dirs, qx - mx, qy - my);
+                    if (wgt != 0.0) F += g[my * RW + (mx - x0)] * (long double)wgt;
+                }
+            acc += (__builtin_popcount(e) & 1) ? -F : F;
+        }
+        out[n] = (double)(acc / den);
+    }
+    free(g);
+    return 0;
+}
+
 int bsfo_num_threads(void)
 {
 #ifdef _OPENMP
