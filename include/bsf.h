@@ -261,7 +261,7 @@ bsf_status bsf_filter_batched(const bsf_config *cfg, int32_t B, const bsf_image_
 
 /*
  * Steps from a covariance field (Section 1.1, eq. cov and eq. geometry; the
- * minimum-kurtosis scales of Section 2.3), for a configuration of four
+ * minimum-kurtosis scales of Section 1.1 and Section 2.4), for a configuration of four
  * directions (any four that span the 2x2 covariances: those of Section 1.1,
  * those of Alg. 3).  cov: FP32 [3][H][W], the planes C11, C12, C22 of each
  * pixel's target covariance in pixel units (x = column, y = row).  sub is
@@ -321,6 +321,38 @@ bsf_status bsf_filter_alg1(const bsf_config *cfg, const float *img, int64_t H, i
 size_t bsf_alg2_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W);
 bsf_status bsf_filter_alg2(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
                            int64_t pitch, const float *cov, float *out, uint8_t *bank_out, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/*
+ * Alg. 3 (Section 2.3, the filter with the box spline of Table 1) as the paper
+ * computes it, in FP64: running sums of the image along the four directions
+ * (step 2), then at every pixel the 16 taps of Table 1 at the shifts of
+ * eq. shifts, each one a value of the running sum between lattice points read
+ * through eq. interpolation with the box spline of one lattice step along each
+ * direction (the paper's beta'_b), weighted +-1 / prod a (step 3).  Generalised
+ * to any four directions: tap t sits at x + sum_k ((s_k - 1)/2 - t_k s_k) u_k
+ * (t_k bit k of t), with sign (-1)^(t_0 + .. + t_3) and weight 1 / prod s_k.  The
+ * result equals the image convolved with the centred box spline of the pixel's
+ * own continuous scales, sampled on the lattice (up to FP64 rounding).
+ *   cfg:   four directions, any distinct canonical ones (the paper's are
+ *          (2,1), (1,2), (1,-2), (2,-1) here: the signs do not change the
+ *          result), order 1, tied, BSF_STEPS_REAL; max_step bounds the steps
+ *          and sizes the LDS rectangle of running sums a tile works in
+ *          (BSF_E_UNSUPPORTED when one pixel's rectangle, (floor(S sum|dx|) +
+ *          sum|dx| + 1) (floor(S sum|dy|) + sum|dy| + 1) FP64 values at
+ *          S = max_step, exceeds 148 KiB: S <= 21 for the paper's directions).
+ *          frac_bits and arith are ignored.
+ *   img:   [H][pitch] of dtype;  steps: FP32 [4][H][W], s_k in lattice steps
+ *          along u_k (the paper's a_k / |u_k|), each in [1, max_step].
+ *   out:   FP32 [H][W] and/or out_f64: FP64 [H][W] (at least one non-NULL).
+ *   ws:    at least bsf_alg3_workspace_bytes (the status block).
+ * A step that is NaN or outside [1, max_step] raises BSF_FLAG_RANGE and gives
+ * that pixel NaN; a non-finite image sample raises BSF_FLAG_NONFINITE and
+ * poisons the outputs of the tiles whose rectangles hold it.
+ */
+size_t bsf_alg3_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W);
+bsf_status bsf_filter_alg3(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
+                           int64_t pitch, const float *steps, float *out, double *out_f64, void *ws, size_t ws_bytes,
                            void *stream);
 
 /*

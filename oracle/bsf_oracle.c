@@ -529,7 +529,7 @@ int bsfo_preintegrate(const void *img, int dtype, long H, long W, long pitch,
 /* (s_k^2 / 12) u_k u_k^T with s_k counted in lattice steps along the integer  */
 /* vector u_k; four directions leave one free parameter, fixed by the minimum  */
 /* kurtosis: the Frobenius norm of sum_k a_k^4 uhat_k uhat_k^T (the matrix of  */
-/* Section 2.3 for the directions of Alg. 3, the same construction for the     */
+/* Section 2.4 for the directions of Alg. 3, the same construction for the     */
 /* directions of Section 1.1), which is sum_k A_k^2 |u_k|^2 u_k u_k^T up to a  */
 /* constant, A_k = s_k^2 / 12.                                                 */
 /* ------------------------------------------------------------------------- */

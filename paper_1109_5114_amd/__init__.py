@@ -57,7 +57,7 @@ EXPORTS = ("bsf_workspace_init", "bsf_plan", "bsf_preintegrate", "bsf_filter_var
            "bsf_filter_batched", "bsf_set_tuning", "bsf_get_tuning", "bsf_read_device_status",
            "bsf_status_string", "bsf_version", "bsf_filter_varying_noalloc", "bsf_cov_to_steps",
            "bsf_alg1_workspace_bytes", "bsf_filter_alg1", "bsf_alg2_workspace_bytes", "bsf_filter_alg2",
-           "bsf_set_box_tile", "bsf_get_box_tile")
+           "bsf_set_box_tile", "bsf_get_box_tile", "bsf_alg3_workspace_bytes", "bsf_filter_alg3")
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -96,6 +96,9 @@ def lib():
         L.bsf_alg2_workspace_bytes.argtypes = [cfgp, i64, i64]
         L.bsf_alg2_workspace_bytes.restype = sz
         L.bsf_filter_alg2.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, sz, P]
+        L.bsf_alg3_workspace_bytes.argtypes = [cfgp, i64, i64]
+        L.bsf_alg3_workspace_bytes.restype = sz
+        L.bsf_filter_alg3.argtypes = [cfgp, i32, P, i64, i64, i64, P, P, P, P, sz, P]
         L.bsf_set_box_tile.argtypes = [i32]
         L.bsf_get_box_tile.argtypes = []
         L.bsf_get_box_tile.restype = i32
@@ -106,7 +109,7 @@ def lib():
                      "bsf_forward_prepare", "bsf_forward_apply",
                      "bsf_filter_backward", "bsf_filter_batched", "bsf_set_tuning",
                      "bsf_read_device_status", "bsf_filter_varying_noalloc", "bsf_cov_to_steps",
-                     "bsf_filter_alg1", "bsf_filter_alg2", "bsf_set_box_tile"):
+                     "bsf_filter_alg1", "bsf_filter_alg2", "bsf_set_box_tile", "bsf_filter_alg3"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -374,6 +377,30 @@ def filter_alg2(cfg: Config, img: torch.Tensor, cov: torch.Tensor, out: Optional
     _check(lib().bsf_filter_alg2(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, _pitch(img), _ptr(cov),
                                  _ptr(out), _ptr(bank), ws.ptr(), ws.nbytes, _stream(img.device)), "bsf_filter_alg2")
     return out
+
+
+def filter_alg3(cfg: Config, img: torch.Tensor, steps: torch.Tensor, out: Optional[torch.Tensor] = None,
+                out_f64: Optional[torch.Tensor] = None, ws: Optional[Workspace] = None):
+    """Alg. 3 in FP64 (bsf_filter_alg3): running sums, the 16 taps of Table 1
+    read through eq. interpolation.  Fills out (float32) and/or out_f64
+    (float64); with neither given, returns a new float32 tensor."""
+    _check_image(img)
+    H, W = img.shape
+    _check_steps(cfg, steps, H, W)
+    if out is None and out_f64 is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=img.device)
+    for t, dt in ((out, torch.float32), (out_f64, torch.float64)):
+        if t is not None and (t.dtype != dt or tuple(t.shape) != (H, W) or not t.is_contiguous()):
+            raise ValueError("outputs must be contiguous [H][W] device tensors of float32 / float64")
+    need = lib().bsf_alg3_workspace_bytes(ctypes.byref(cfg.c()), H, W)
+    if need == 0:
+        raise BsfError(E_UNSUPPORTED, "bsf_alg3_workspace_bytes")
+    ws = ws or _workspace(img.device, need)
+    ws.ensure(need)
+    _check(lib().bsf_filter_alg3(ctypes.byref(cfg.c()), _dtype_code(img), _ptr(img), H, W, _pitch(img),
+                                 _ptr(steps), _ptr(out), _ptr(out_f64), ws.ptr(), ws.nbytes, _stream(img.device)),
+           "bsf_filter_alg3")
+    return out if out is not None else out_f64
 
 
 def forward_prepare(cfg: Config, img: torch.Tensor, steps: torch.Tensor, ws: Workspace,

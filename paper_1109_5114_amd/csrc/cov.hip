@@ -1,5 +1,5 @@
 // Steps from a covariance field (Section 1.1, eq. cov and eq. geometry; the
-// minimum-kurtosis choice of the scales, Section 2.3).
+// minimum-kurtosis choice of the scales, Section 1.1 and Section 2.4).
 //
 // A box spline with one box of s_k lattice steps along each integer direction
 // u_k has covariance sum_k A_k u_k u_k^T, A_k = s_k^2 / 12 (a length-s box has

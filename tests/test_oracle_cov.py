@@ -1,5 +1,5 @@
 """Pins of the oracle's covariance -> steps mapping (eq. cov, eq. geometry,
-eq. boundE, condition2, the minimum-kurtosis choice of Section 2.3) and of the
+eq. boundE, condition2, the minimum-kurtosis choice of Section 2.4) and of the
 sector rule of Alg. 2, against what the paper prints: the covariance matrices
 of both four-direction box splines in terms of their scales, the isotropic
 scale sqrt(6) sigma, the kurtosis matrix of the second box spline, the
@@ -35,7 +35,7 @@ def paper_cov_bank2(a):
 
 def paper_kurtosis_bank2(a):
     """Kurtosis matrix of the box spline of Alg. 3, up to the constant kappa/5
-    (Section 2.3)."""
+    (Section 2.4)."""
     a1, a2, a3, a4 = np.asarray(a) ** 4
     return np.array([[4 * a1 + a2 + a3 + 4 * a4, 2 * (a1 + a2 - a3 - a4)],
                      [2 * (a1 + a2 - a3 - a4), a1 + 4 * a2 + 4 * a3 + a4]])

@@ -196,3 +196,27 @@ def workload5(B=16, H=1024, W=1024, seed=SEED0 + 4):
     return dict(name="forward+adjoint %dx %dx%d order-2 tied" % (B, H, W), imgs=imgs,
                 steps=steps, gout=gout, dirs=DIRS4, order=2, tied=True, mode="real",
                 max_step=20.0, fd_crop=(480, 544, 480, 544))
+
+
+# The directions of Alg. 3 / Table 1, in the library's canonical sign
+# ((-1,2) and (-2,1) turned to (1,-2) and (2,-1)).
+DIRS_TABLE1 = ((2, 1), (1, 2), (1, -2), (2, -1))
+
+
+def workload_alg3(H=4096, W=4096, seed=SEED0 + 5):
+    """The image of workload2 (FP32 uniform[0,1) with 5% salt-and-pepper) and a
+    per-pixel elliptical covariance from smooth fields for the box spline of
+    Table 1: orientation in [0, pi), elongation in [1, 6], sigma in [2, 12] px.
+    Returns img and cov [3][H][W] float32 (C11, C12, C22); the steps are the
+    minimum-kurtosis scales of that box spline for cov."""
+    rng = np.random.default_rng(seed)
+    img = _uniform_image(rng, H, W)
+    mask = rng.random((H, W)) < 0.05
+    salt = (rng.random((H, W)) < 0.5).astype(np.float32)
+    img = np.where(mask, salt, img).astype(np.float32)
+    theta = smooth(rng, H, W, 0.0, math.pi)
+    rho = smooth(rng, H, W, 1.0, 6.0)
+    sigma = smooth(rng, H, W, 2.0, 12.0)
+    cov = np.stack(cov_field(theta, rho, sigma)).astype(np.float32)
+    return dict(name="Alg. 3 %dx%d fp32 covariance field" % (H, W), img=img, cov=cov,
+                dirs=DIRS_TABLE1, order=1, tied=True, mode="real", max_step=21.0)
