@@ -33,29 +33,48 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <utility>
 
 #include "bsf_common.h"
 
 namespace bsf {
 namespace {
 
-constexpr int kA3Tile = 16;             // pixels per tile side
-constexpr int kA3Threads = 256;         // one thread per pixel of a whole tile
-constexpr size_t kA3CapDefault = 8192;  // window elements (64 KiB) when the steps allow it
-constexpr size_t kA3CapMax = 18944;     // window elements (148 KiB): the largest LDS buffer
+constexpr int kA3Tile = 16;        // pixels per tile side
+constexpr int kA3Threads = 256;    // one thread per pixel of a whole tile
+constexpr int kA3CapMax = 18944;   // window elements (148 KiB): the largest LDS buffer
+// Launch tiers: a tile first goes to a launch whose LDS buffer holds kA3Tier[0]
+// elements (four blocks per CU); a tile whose rectangle does not fit there,
+// even in 4 x 4 pieces, is queued for the next tier, whose buffer is larger
+// and whose blocks work through the queue.  The last tier's buffer holds any
+// one pixel's rectangle at max_step.
+constexpr int kA3Tier[2] = {4096, 8192};
+constexpr int kA3MinPiece = 4;     // smallest piece of a tile outside the last tier
 
-// Constants of the unit box spline of four directions.
+enum A3StatusWord : int {
+    ST_A3_QUEUED0 = 28,  // tiles queued by the first tier
+    ST_A3_QUEUED1 = 29,  // tiles queued by the second
+};
+
+// Constants of the unit box spline of four directions.  Frame coordinates of
+// a point p: in Q's frame gamma = (p x u3) / det23, delta = (u2 x p) / det23,
+// in P's frame alpha = (p x u1) / det01, beta = (u0 x p) / det01 (P = [-1/2,
+// 1/2]^2 in (alpha, beta), Q likewise in (gamma, delta)).  Each parallelogram's
+// edges come in mirror pairs (edge i + 2 is edge i through the centre), so two
+// edges per parallelogram carry all the constants.
 struct A3Geom {
-    double u[4][2];        // P spans (u0, u1), Q spans (u2, u3), each pair counter-clockwise
-    double inv01, inv23;   // 1 / det(u0, u1), 1 / det(u2, u3)
-    double pg[4], pd[4];   // P's edge starts a_i in Q's frame: gamma(a_i), delta(a_i)
-    double prg[4], prd[4]; // 1 / gamma(d_i), 1 / delta(d_i) of P's edge directions
-    double pc[4];          // a_i x d_i
-    double qa[4], qb[4];   // Q's edge starts b_j (about Q's centre) in P's frame: alpha(b_j), beta(b_j)
-    double qra[4], qrb[4]; // 1 / alpha(e_j), 1 / beta(e_j) of Q's edge directions
-    double qc[4];          // b_j x e_j
-    double qe[4][2];       // e_j
-    double ex, ey;         // reach of beta_b: half the sums of |dx| and of |dy|
+    double fg[2], fd[2], fa[2], fb[2];  // gamma = fg . p, delta = fd . p, alpha = fa . p, beta = fb . p
+    double pg[2], pd[2];    // P's edge i from a_i along d_i: gamma(a_i), delta(a_i)
+    double prg[2], prd[2];  // 1 / gamma(d_i), 1 / delta(d_i)
+    double pc[2];           // a_i x d_i
+    double qa[2], qb[2];    // Q's edge j from b_j (about Q's centre) along e_j: alpha(b_j), beta(b_j)
+    double qra[2], qrb[2];  // 1 / alpha(e_j), 1 / beta(e_j)
+    double qc[2];           // b_j x e_j
+    double det23;           // p x e_0 = -det23 delta(p), p x e_1 = det23 gamma(p) (e_0 = u2, e_1 = u3)
+    double scale;           // 1 / (2 det01 det23)
+    // the support: |n_k . p| < h_k, n_k normal to u_k, h_k = (1/2) sum_j |n_k . u_j|
+    double ny[4], h[4], rnx[4];  // rnx = 1 / n_k.x (0 when n_k.x = 0)
+    double ex, ey;               // half the sums of |dx| and of |dy|
 };
 
 struct A3Args {
@@ -68,12 +87,9 @@ struct A3Args {
     int32_t *status;
     int dx[4], dy[4];
     float max_step;
-    int cap;               // window elements the LDS buffer holds
     int64_t tiles_x, tiles;
     A3Geom g;
 };
-
-__device__ __forceinline__ double cross2(double ax, double ay, double bx, double by) { return ax * by - ay * bx; }
 
 // Narrow [t0, t1] to the t with |v + t dv| <= 1/2 (r = 1 / dv, dv != 0).
 __device__ __forceinline__ void slab(double v, double r, double &t0, double &t1) {
@@ -83,28 +99,29 @@ __device__ __forceinline__ void slab(double v, double r, double &t0, double &t1)
 }
 
 // beta_b(p): the overlap of P (about 0) and Q (about p), over |P| |Q|.
-__device__ double unit_box_spline(const A3Geom &G, double px, double py) {
-    // p in Q's frame and in P's frame
-    const double gp = cross2(px, py, G.u[3][0], G.u[3][1]) * G.inv23;
-    const double dp = cross2(G.u[2][0], G.u[2][1], px, py) * G.inv23;
-    const double ap = cross2(px, py, G.u[1][0], G.u[1][1]) * G.inv01;
-    const double bp = cross2(G.u[0][0], G.u[0][1], px, py) * G.inv01;
+__device__ __forceinline__ double unit_box_spline(const A3Geom &G, double px, double py) {
+    const double gp = G.fg[0] * px + G.fg[1] * py, dp = G.fd[0] * px + G.fd[1] * py;
+    const double ap = G.fa[0] * px + G.fa[1] * py, bp = G.fb[0] * px + G.fb[1] * py;
     double twice = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {  // P's edges inside Q
-        double t0 = 0.0, t1 = 1.0;
+    for (int i = 0; i < 2; ++i) {
+        // P's edge i and its mirror, in Q's frame about p
+        double t0 = 0.0, t1 = 1.0, m0 = 0.0, m1 = 1.0;
         slab(G.pg[i] - gp, G.prg[i], t0, t1);
         slab(G.pd[i] - dp, G.prd[i], t0, t1);
-        twice += fmax(t1 - t0, 0.0) * G.pc[i];
+        slab(-G.pg[i] - gp, -G.prg[i], m0, m1);
+        slab(-G.pd[i] - dp, -G.prd[i], m0, m1);
+        twice += (fmax(t1 - t0, 0.0) + fmax(m1 - m0, 0.0)) * G.pc[i];
+        // Q's edge i and its mirror, in P's frame
+        double s0 = 0.0, s1 = 1.0, n0 = 0.0, n1 = 1.0;
+        slab(G.qa[i] + ap, G.qra[i], s0, s1);
+        slab(G.qb[i] + bp, G.qrb[i], s0, s1);
+        slab(-G.qa[i] + ap, -G.qra[i], n0, n1);
+        slab(-G.qb[i] + bp, -G.qrb[i], n0, n1);
+        const double pe = i == 0 ? -G.det23 * dp : G.det23 * gp;  // p x e_i
+        twice += fmax(s1 - s0, 0.0) * (G.qc[i] + pe) + fmax(n1 - n0, 0.0) * (G.qc[i] - pe);
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {  // Q's edges inside P
-        double t0 = 0.0, t1 = 1.0;
-        slab(G.qa[j] + ap, G.qra[j], t0, t1);
-        slab(G.qb[j] + bp, G.qrb[j], t0, t1);
-        twice += fmax(t1 - t0, 0.0) * (G.qc[j] + cross2(px, py, G.qe[j][0], G.qe[j][1]));
-    }
-    return 0.5 * twice * G.inv01 * G.inv23;
+    return twice * G.scale;
 }
 
 __device__ __forceinline__ double a3_sample(const A3Args &a, int64_t x, int64_t y, bool &nonfinite) {
@@ -134,18 +151,56 @@ struct Ext {
     int lx, hx, ly, hy;
 };
 
-__global__ __launch_bounds__(kA3Threads) void k_alg3(A3Args a) {
-    extern __shared__ double win[];
-    __shared__ double s_red[kA3Threads];
-    __shared__ Ext s_wave[kA3Threads / 64];
-    __shared__ unsigned char s_live[kA3Threads];
-    __shared__ int s_nonfinite;
+struct A3Shared {
+    double red[kA3Threads];
+    Ext wave[kA3Threads / 64];
+    unsigned char live[kA3Threads];
+};
+
+// F(q) of eq. interpolation at the tap q = pixel + (qx, qy): the running sums
+// at the lattice points of beta_b's support around q, row by row (the
+// support's cross-section at each row bounds the columns), weighted by
+// beta_b(q - m).  (ox, oy) is the pixel inside the WX x WY rectangle.
+__device__ __forceinline__ double interpolate(const A3Geom &G, const double *win, int WX, int WY, int ox, int oy,
+                                              double qx, double qy) {
+    const int mx0 = (int)ceil(qx - G.ex), mx1 = (int)floor(qx + G.ex);
+    const int my0 = (int)ceil(qy - G.ey), my1 = (int)floor(qy + G.ey);
+    double F = 0.0;
+    for (int my = my0; my <= my1; ++my) {
+        const int iy = oy + my;
+        if ((unsigned)iy >= (unsigned)WY) continue;
+        const double py = qy - my;
+        double xl = -G.ex, xr = G.ex;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (G.rnx[k] != 0.0) {
+                const double c = -G.ny[k] * py;
+                const double t1 = (c - G.h[k]) * G.rnx[k], t2 = (c + G.h[k]) * G.rnx[k];
+                xl = fmax(xl, fmin(t1, t2));
+                xr = fmin(xr, fmax(t1, t2));
+            } else if (fabs(G.ny[k] * py) >= G.h[k]) {
+                xr = xl - 1.0;  // the row misses the support
+            }
+        }
+        const int lo = max(mx0, (int)ceil(qx - xr)), hi = min(mx1, (int)floor(qx - xl));
+        for (int mx = lo; mx <= hi; ++mx) {
+            const int ix = ox + mx;
+            if ((unsigned)ix >= (unsigned)WX) continue;
+            F += win[iy * WX + ix] * unit_box_spline(G, qx - mx, py);
+        }
+    }
+    return F;
+}
+
+// One tile: the rectangle of every piece of it that fits `cap` window
+// elements, at pieces of at least b_min pixels a side; a tile that fits no
+// such piece goes to q_out (NULL in the last tier, whose buffer fits one pixel).
+__device__ void a3_tile(const A3Args &a, int64_t tile, int cap, int b_min, int32_t *q_out, int32_t *n_out,
+                        double *win, A3Shared &sh, bool &nonfinite) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t tile = xcd_item(blockIdx.x, a.tiles);
-    if (tile >= a.tiles) return;
     const int64_t x0 = (tile % a.tiles_x) * kA3Tile, y0 = (tile / a.tiles_x) * kA3Tile;
     const int64_t HW = a.H * a.W;
-    const double ex = a.g.ex, ey = a.g.ey;
+    const A3Geom &G = a.g;
 
     // 1. each pixel's steps and the offsets of the lattice points its taps read
     Ext e{INT_MAX, INT_MIN, INT_MAX, INT_MIN};
@@ -165,23 +220,20 @@ __global__ __launch_bounds__(kA3Threads) void k_alg3(A3Args a) {
                 for (int t = 0; t < 16; ++t) {
                     double qx, qy;
                     tap_offset(a, s, t, qx, qy);
-                    e.lx = min(e.lx, (int)ceil(qx - ex));
-                    e.hx = max(e.hx, (int)floor(qx + ex));
-                    e.ly = min(e.ly, (int)ceil(qy - ey));
-                    e.hy = max(e.hy, (int)floor(qy + ey));
+                    e.lx = min(e.lx, (int)ceil(qx - G.ex));
+                    e.hx = max(e.hx, (int)floor(qx + G.ex));
+                    e.ly = min(e.ly, (int)ceil(qy - G.ey));
+                    e.hy = max(e.hy, (int)floor(qy + G.ey));
                 }
-                ok = (int64_t)(e.hx - e.lx + 1) * (e.hy - e.ly + 1) <= a.cap;
-            }
-            if (!ok) {
+            } else {
                 atomicOr((unsigned *)&a.status[ST_FLAGS], BSF_FLAG_RANGE);
                 if (a.out) a.out[p] = __builtin_nanf("");
                 if (a.out64) a.out64[p] = __builtin_nan("");
-                e = Ext{INT_MAX, INT_MIN, INT_MAX, INT_MIN};
             }
             live = ok;
         }
     }
-    s_live[tid] = live;
+    sh.live[tid] = live;
     Ext t = e;
     for (int d = 32; d >= 1; d >>= 1) {
         t.lx = min(t.lx, __shfl_xor(t.lx, d, 64));
@@ -189,41 +241,45 @@ __global__ __launch_bounds__(kA3Threads) void k_alg3(A3Args a) {
         t.ly = min(t.ly, __shfl_xor(t.ly, d, 64));
         t.hy = max(t.hy, __shfl_xor(t.hy, d, 64));
     }
-    if (lane == 0) s_wave[wave] = t;
-    if (tid == 0) s_nonfinite = 0;
+    if (lane == 0) sh.wave[wave] = t;
     __syncthreads();
-    Ext T = s_wave[0];
+    Ext T = sh.wave[0];
     for (int w = 1; w < kA3Threads / 64; ++w) {
-        T.lx = min(T.lx, s_wave[w].lx);
-        T.hx = max(T.hx, s_wave[w].hx);
-        T.ly = min(T.ly, s_wave[w].ly);
-        T.hy = max(T.hy, s_wave[w].hy);
+        T.lx = min(T.lx, sh.wave[w].lx);
+        T.hx = max(T.hx, sh.wave[w].hx);
+        T.ly = min(T.ly, sh.wave[w].ly);
+        T.hy = max(T.hy, sh.wave[w].hy);
     }
-    if (T.lx == INT_MAX) return;  // no live pixel in the tile (block-uniform)
+    if (T.lx == INT_MAX) {  // no live pixel in the tile (block-uniform)
+        __syncthreads();
+        return;
+    }
 
-    // 2. the largest sub-tile whose rectangle, with the tile's offsets, fits.
-    //    One pixel always fits: the offsets of any pixel with steps up to
-    //    max_step lie within the span the buffer was sized for.
+    // 2. the largest piece whose rectangle, with the tile's offsets, fits
     int b = kA3Tile;
-    while (b > 1 && (int64_t)(b + T.hx - T.lx) * (b + T.hy - T.ly) > a.cap) b >>= 1;
+    while (b > b_min && (int64_t)(b + T.hx - T.lx) * (b + T.hy - T.ly) > cap) b >>= 1;
+    if ((int64_t)(b + T.hx - T.lx) * (b + T.hy - T.ly) > cap) {
+        if (q_out) {
+            if (tid == 0) q_out[atomicAdd(n_out, 1)] = (int32_t)tile;
+        } else {
+            // not reached: the last buffer holds one pixel's rectangle at max_step
+            if (live) {
+                const int64_t p = (y0 + tid / kA3Tile) * a.W + x0 + tid % kA3Tile;
+                if (a.out) a.out[p] = __builtin_nanf("");
+                if (a.out64) a.out64[p] = __builtin_nan("");
+            }
+            if (tid == 0) atomicOr((unsigned *)&a.status[ST_FLAGS], BSF_FLAG_RANGE);
+        }
+        __syncthreads();
+        return;
+    }
     const int per_side = kA3Tile / b, tpp = min(16, kA3Threads / (b * b));
-    bool nonfinite = false;
+    const int WX = b + T.hx - T.lx, WY = b + T.hy - T.ly;
     for (int sub = 0; sub < per_side * per_side; ++sub) {
         const int sx0 = (sub % per_side) * b, sy0 = (sub / per_side) * b;
         if (x0 + sx0 >= a.W || y0 + sy0 >= a.H) continue;  // block-uniform
-        const Ext E = T;
-        const int64_t wx0 = x0 + sx0 + E.lx, wy0 = y0 + sy0 + E.ly;
-        const int WX = b + E.hx - E.lx, WY = b + E.hy - E.ly;
-        if ((int64_t)WX * WY > a.cap) {  // not reached for steps within max_step; never overrun the buffer
-            const int64_t x = x0 + sx0 + tid % b, y = y0 + sy0 + tid / b;
-            if (tid < b * b && x < a.W && y < a.H) {
-                if (a.out) a.out[y * a.W + x] = __builtin_nanf("");
-                if (a.out64) a.out64[y * a.W + x] = __builtin_nan("");
-            }
-            if (tid == 0) atomicOr((unsigned *)&a.status[ST_FLAGS], BSF_FLAG_RANGE);
-            continue;
-        }
-        __syncthreads();  // the previous sub-tile is done with the buffer
+        const int64_t wx0 = x0 + sx0 + T.lx, wy0 = y0 + sy0 + T.ly;
+        __syncthreads();  // the previous piece is done with the buffer
         for (int i = tid; i < WX * WY; i += kA3Threads)
             win[i] = a3_sample(a, wx0 + i % WX, wy0 + i / WX, nonfinite);
         __syncthreads();
@@ -254,9 +310,9 @@ __global__ __launch_bounds__(kA3Threads) void k_alg3(A3Args a) {
         }
         // step 3: the taps, tpp threads per pixel
         const int pi = tid / tpp, grp = tid % tpp;
-        const int lx_ = pi % b, ly_ = pi / b;
-        const int64_t px = x0 + sx0 + lx_, py = y0 + sy0 + ly_;
-        const bool mine = pi < b * b && px < a.W && py < a.H && s_live[(sy0 + ly_) * kA3Tile + sx0 + lx_];
+        const int lx = pi % b, ly = pi / b;
+        const int64_t px = x0 + sx0 + lx, py = y0 + sy0 + ly;
+        const bool mine = pi < b * b && px < a.W && py < a.H && sh.live[(sy0 + ly) * kA3Tile + sx0 + lx];
         double acc = 0.0, den = 1.0;
         if (mine) {
             const int64_t p = py * a.W + px;
@@ -266,40 +322,59 @@ __global__ __launch_bounds__(kA3Threads) void k_alg3(A3Args a) {
                 s[k] = a.steps[k * HW + p];
                 den *= s[k];
             }
-            // the pixel's offset inside the rectangle
             const int ox = (int)(px - wx0), oy = (int)(py - wy0);
             for (int tap = grp; tap < 16; tap += tpp) {
                 double qx, qy;
                 tap_offset(a, s, tap, qx, qy);
-                const int mx0 = (int)ceil(qx - ex), mx1 = (int)floor(qx + ex);
-                const int my0 = (int)ceil(qy - ey), my1 = (int)floor(qy + ey);
-                double F = 0.0;
-                for (int my = my0; my <= my1; ++my) {
-                    const int iy = oy + my;
-                    if ((unsigned)iy >= (unsigned)WY) continue;
-                    for (int mx = mx0; mx <= mx1; ++mx) {
-                        const int ix = ox + mx;
-                        if ((unsigned)ix >= (unsigned)WX) continue;
-                        F += win[iy * WX + ix] * unit_box_spline(a.g, qx - mx, qy - my);
-                    }
-                }
+                const double F = interpolate(G, win, WX, WY, ox, oy, qx, qy);
                 acc += (__builtin_popcount(tap) & 1) ? -F : F;
             }
         }
-        s_red[tid] = acc;
+        sh.red[tid] = acc;
         __syncthreads();
         if (mine && grp == 0) {
             double v = 0.0;
-            for (int j = 0; j < tpp; ++j) v += s_red[tid + j];
+            for (int j = 0; j < tpp; ++j) v += sh.red[tid + j];
             v /= den;
             const int64_t p = py * a.W + px;
             if (a.out) a.out[p] = (float)v;
             if (a.out64) a.out64[p] = v;
         }
     }
-    if (nonfinite) s_nonfinite = 1;
-    __syncthreads();
-    if (tid == 0 && s_nonfinite) atomicOr((unsigned *)&a.status[ST_FLAGS], BSF_FLAG_NONFINITE);
+    __syncthreads();  // the shared words are free for the next tile
+}
+
+__global__ void k_alg3_begin(int32_t *status) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        status[ST_A3_QUEUED0] = 0;
+        status[ST_A3_QUEUED1] = 0;
+    }
+}
+
+__device__ __forceinline__ void flag_nonfinite(const A3Args &a, bool nonfinite) {
+    if (__any(nonfinite) && (threadIdx.x & 63) == 0) atomicOr((unsigned *)&a.status[ST_FLAGS], BSF_FLAG_NONFINITE);
+}
+
+// First tier: one block per tile, in XCD order.
+__global__ __launch_bounds__(kA3Threads) void k_alg3_tiles(A3Args a, int cap, int b_min, int32_t *q_out,
+                                                           int32_t *n_out) {
+    extern __shared__ double win[];
+    __shared__ A3Shared sh;
+    const int64_t tile = xcd_item(blockIdx.x, a.tiles);
+    bool nonfinite = false;
+    if (tile < a.tiles) a3_tile(a, tile, cap, b_min, q_out, n_out, win, sh, nonfinite);
+    flag_nonfinite(a, nonfinite);
+}
+
+// Later tiers: blocks work through the tiles the previous tier queued.
+__global__ __launch_bounds__(kA3Threads) void k_alg3_queue(A3Args a, int cap, int b_min, const int32_t *q_in,
+                                                           const int32_t *n_in, int32_t *q_out, int32_t *n_out) {
+    extern __shared__ double win[];
+    __shared__ A3Shared sh;
+    const int n = *n_in;
+    bool nonfinite = false;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) a3_tile(a, q_in[i], cap, b_min, q_out, n_out, win, sh, nonfinite);
+    flag_nonfinite(a, nonfinite);
 }
 
 // Host: the constants of beta_b for four directions (the first two span P, the
@@ -315,49 +390,56 @@ bsf_status make_a3_geom(const int dx[4], const int dy[4], A3Geom *G) {
         const double det = v0[0] * v1[1] - v0[1] * v1[0];
         if (det == 0.0) return BSF_E_INVALID;
         if (det < 0.0)
-            for (int c = 0; c < 2; ++c) {
-                const double t = v0[c];
-                v0[c] = v1[c];
-                v1[c] = t;
-            }
+            for (int c = 0; c < 2; ++c) std::swap(v0[c], v1[c]);
     }
-    for (int k = 0; k < 4; ++k)
-        for (int c = 0; c < 2; ++c) G->u[k][c] = u[k][c];
-    const double det01 = u[0][0] * u[1][1] - u[0][1] * u[1][0];
-    const double det23 = u[2][0] * u[3][1] - u[2][1] * u[3][0];
-    G->inv01 = 1.0 / det01;
-    G->inv23 = 1.0 / det23;
     auto cr = [](const double *a, const double *b) { return a[0] * b[1] - a[1] * b[0]; };
-    // corners (-,-), (+,-), (+,+), (-,+) and edges +v0, +v1, -v0, -v1: counter-clockwise
-    const double sg[4][2] = {{-0.5, -0.5}, {0.5, -0.5}, {0.5, 0.5}, {-0.5, 0.5}};
-    const double sd[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
-    for (int i = 0; i < 4; ++i) {
+    const double det01 = cr(u[0], u[1]), det23 = cr(u[2], u[3]);
+    // p x v = p.x v.y - p.y v.x; v x p = v.x p.y - v.y p.x
+    G->fg[0] = u[3][1] / det23;
+    G->fg[1] = -u[3][0] / det23;
+    G->fd[0] = -u[2][1] / det23;
+    G->fd[1] = u[2][0] / det23;
+    G->fa[0] = u[1][1] / det01;
+    G->fa[1] = -u[1][0] / det01;
+    G->fb[0] = -u[0][1] / det01;
+    G->fb[1] = u[0][0] / det01;
+    auto frame = [](const double f[2], const double *v) { return f[0] * v[0] + f[1] * v[1]; };
+    // edges 0 and 1 of each parallelogram: from (-,-) along +v0, from (+,-) along +v1
+    const double sg[2][2] = {{-0.5, -0.5}, {0.5, -0.5}};
+    const double sd[2][2] = {{1, 0}, {0, 1}};
+    for (int i = 0; i < 2; ++i) {
         const double a[2] = {sg[i][0] * u[0][0] + sg[i][1] * u[1][0], sg[i][0] * u[0][1] + sg[i][1] * u[1][1]};
         const double d[2] = {sd[i][0] * u[0][0] + sd[i][1] * u[1][0], sd[i][0] * u[0][1] + sd[i][1] * u[1][1]};
-        G->pg[i] = cr(a, u[3]) * G->inv23;
-        G->pd[i] = cr(u[2], a) * G->inv23;
-        const double gd = cr(d, u[3]) * G->inv23, dd = cr(u[2], d) * G->inv23;
-        if (gd == 0.0 || dd == 0.0) return BSF_E_INVALID;  // parallel edges
+        G->pg[i] = frame(G->fg, a);
+        G->pd[i] = frame(G->fd, a);
+        const double gd = frame(G->fg, d), dd = frame(G->fd, d);
+        if (gd == 0.0 || dd == 0.0) return BSF_E_INVALID;  // an edge of P parallel to one of Q
         G->prg[i] = 1.0 / gd;
         G->prd[i] = 1.0 / dd;
         G->pc[i] = cr(a, d);
         const double b[2] = {sg[i][0] * u[2][0] + sg[i][1] * u[3][0], sg[i][0] * u[2][1] + sg[i][1] * u[3][1]};
         const double e[2] = {sd[i][0] * u[2][0] + sd[i][1] * u[3][0], sd[i][0] * u[2][1] + sd[i][1] * u[3][1]};
-        G->qa[i] = cr(b, u[1]) * G->inv01;
-        G->qb[i] = cr(u[0], b) * G->inv01;
-        const double ad = cr(e, u[1]) * G->inv01, bd = cr(u[0], e) * G->inv01;
+        G->qa[i] = frame(G->fa, b);
+        G->qb[i] = frame(G->fb, b);
+        const double ad = frame(G->fa, e), bd = frame(G->fb, e);
         if (ad == 0.0 || bd == 0.0) return BSF_E_INVALID;
         G->qra[i] = 1.0 / ad;
         G->qrb[i] = 1.0 / bd;
         G->qc[i] = cr(b, e);
-        G->qe[i][0] = e[0];
-        G->qe[i][1] = e[1];
     }
+    G->det23 = det23;
+    G->scale = 0.5 / (det01 * det23);
     G->ex = 0.0;
     G->ey = 0.0;
     for (int k = 0; k < 4; ++k) {
-        G->ex += 0.5 * fabs((double)dx[k]);
-        G->ey += 0.5 * fabs((double)dy[k]);
+        G->ex += 0.5 * std::abs(dx[k]);
+        G->ey += 0.5 * std::abs(dy[k]);
+        const double nx = -dy[k], ny = dx[k];
+        double h = 0.0;
+        for (int j = 0; j < 4; ++j) h += 0.5 * std::fabs(nx * dx[j] + ny * dy[j]);
+        G->ny[k] = ny;
+        G->h[k] = h;
+        G->rnx[k] = nx != 0.0 ? 1.0 / nx : 0.0;
     }
     return BSF_OK;
 }
@@ -374,15 +456,28 @@ int64_t a3_window(const Plan &p, int b) {
     return (b + (int64_t)floor(S * sx) + sx) * (b + (int64_t)floor(S * sy) + sy);
 }
 
-bsf_status a3_check(const bsf_config *cfg, int64_t H, int64_t W, Plan &p, size_t &cap) {
+// The launch tiers for a plan: buffer sizes in window elements, the last one
+// holding any single pixel's rectangle (and a whole tile's when it is small).
+struct A3Tiers {
+    int n;
+    int cap[3];
+};
+
+bsf_status a3_check(const bsf_config *cfg, int64_t H, int64_t W, Plan &p, A3Tiers &t) {
     bsf_status r = make_plan(cfg, H, W, &p);
     if (r != BSF_OK) return r;
     if (p.n_dirs != 4 || p.order != 1 || p.mode != BSF_STEPS_REAL || !p.tied) return BSF_E_UNSUPPORTED;
     const int64_t one = a3_window(p, 1), whole = a3_window(p, kA3Tile);
-    if (one > (int64_t)kA3CapMax) return BSF_E_UNSUPPORTED;  // max_step too large for the LDS buffer
-    cap = (size_t)std::max<int64_t>(std::min<int64_t>(whole, kA3CapDefault), one);
+    if (one > kA3CapMax) return BSF_E_UNSUPPORTED;  // max_step too large for the LDS buffer
+    const int last = (int)std::max<int64_t>(std::min<int64_t>(whole, kA3Tier[1]), one);
+    t.n = 0;
+    for (int c : kA3Tier)
+        if (c < last) t.cap[t.n++] = c;
+    t.cap[t.n++] = last;
     return BSF_OK;
 }
+
+size_t a3_queue_bytes(int64_t tiles) { return align_up((size_t)tiles * sizeof(int32_t)); }
 
 }  // namespace
 }  // namespace bsf
@@ -393,22 +488,23 @@ extern "C" {
 
 size_t bsf_alg3_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W) {
     Plan p;
-    size_t cap;
-    if (a3_check(cfg, H, W, p, cap) != BSF_OK) return 0;
-    return kStatusBytes;
+    A3Tiers t;
+    if (a3_check(cfg, H, W, p, t) != BSF_OK) return 0;
+    const int64_t tiles = ((W + kA3Tile - 1) / kA3Tile) * ((H + kA3Tile - 1) / kA3Tile);
+    return kStatusBytes + 2 * a3_queue_bytes(tiles);
 }
 
 bsf_status bsf_filter_alg3(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
                            int64_t pitch, const float *steps, float *out, double *out_f64, void *ws, size_t ws_bytes,
                            void *stream) {
     Plan p;
-    size_t cap;
-    bsf_status r = a3_check(cfg, H, W, p, cap);
+    A3Tiers tiers;
+    bsf_status r = a3_check(cfg, H, W, p, tiers);
     if (r != BSF_OK) return r;
     const int kind = dtype == BSF_U8 ? SRC_U8 : dtype == BSF_U16 ? SRC_U16 : dtype == BSF_F32 ? SRC_F32 : -1;
     if (kind < 0 || !ws || pitch < W || (H * W > 0 && (!img || !steps || (!out && !out_f64))))
         return BSF_E_INVALID;
-    if (ws_bytes < kStatusBytes) return BSF_E_WORKSPACE;
+    if (ws_bytes < bsf_alg3_workspace_bytes(cfg, H, W)) return BSF_E_WORKSPACE;
     if (H * W == 0) return BSF_OK;
     A3Args a{};
     a.img = img;
@@ -425,21 +521,38 @@ bsf_status bsf_filter_alg3(const bsf_config *cfg, bsf_dtype dtype, const void *i
         a.dy[k] = p.dy[k];
     }
     a.max_step = p.max_step;
-    a.cap = (int)cap;
     r = make_a3_geom(a.dx, a.dy, &a.g);
     if (r != BSF_OK) return r;
     a.tiles_x = (W + kA3Tile - 1) / kA3Tile;
     a.tiles = a.tiles_x * ((H + kA3Tile - 1) / kA3Tile);
+    int32_t *queue[2] = {reinterpret_cast<int32_t *>(static_cast<char *>(ws) + kStatusBytes),
+                         reinterpret_cast<int32_t *>(static_cast<char *>(ws) + kStatusBytes + a3_queue_bytes(a.tiles))};
+    int32_t *queued[2] = {a.status + ST_A3_QUEUED0, a.status + ST_A3_QUEUED1};
     hipStream_t st = static_cast<hipStream_t>(stream);
     static bool s_big_lds = false;  // allow the largest buffer once per process
     if (!s_big_lds) {
-        BSF_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_alg3),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)(kA3CapMax * sizeof(double))));
+        for (const void *k : {reinterpret_cast<const void *>(k_alg3_tiles), reinterpret_cast<const void *>(k_alg3_queue)})
+            BSF_HIP_CHECK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)(kA3CapMax * sizeof(double))));
         s_big_lds = true;
     }
-    hipLaunchKernelGGL(k_alg3, dim3((unsigned)xcd_grid(a.tiles)), dim3(kA3Threads), cap * sizeof(double), st, a);
+    hipLaunchKernelGGL(k_alg3_begin, dim3(1), dim3(64), 0, st, a.status);
     BSF_HIP_CHECK(hipGetLastError());
+    for (int i = 0; i < tiers.n; ++i) {
+        const bool last = i == tiers.n - 1;
+        const int cap = tiers.cap[i], b_min = last ? 1 : kA3MinPiece;
+        int32_t *q_out = last ? nullptr : queue[i % 2], *n_out = last ? nullptr : queued[i % 2];
+        const size_t lds = (size_t)cap * sizeof(double);
+        if (i == 0) {
+            hipLaunchKernelGGL(k_alg3_tiles, dim3((unsigned)xcd_grid(a.tiles)), dim3(kA3Threads), lds, st, a, cap,
+                               b_min, q_out, n_out);
+        } else {
+            const unsigned grid = (unsigned)std::min<int64_t>(a.tiles, 2048);
+            hipLaunchKernelGGL(k_alg3_queue, dim3(grid), dim3(kA3Threads), lds, st, a, cap, b_min,
+                               queue[(i - 1) % 2], queued[(i - 1) % 2], q_out, n_out);
+        }
+        BSF_HIP_CHECK(hipGetLastError());
+    }
     return BSF_OK;
 }
 
