@@ -56,26 +56,115 @@ enum A3StatusWord : int {
     ST_A3_QUEUED1 = 29,  // tiles queued by the second
 };
 
-// Constants of the unit box spline of four directions.  Frame coordinates of
-// a point p: in Q's frame gamma = (p x u3) / det23, delta = (u2 x p) / det23,
-// in P's frame alpha = (p x u1) / det01, beta = (u0 x p) / det01 (P = [-1/2,
-// 1/2]^2 in (alpha, beta), Q likewise in (gamma, delta)).  Each parallelogram's
-// edges come in mirror pairs (edge i + 2 is edge i through the centre), so two
-// edges per parallelogram carry all the constants.
-struct A3Geom {
-    double fg[2], fd[2], fa[2], fb[2];  // gamma = fg . p, delta = fd . p, alpha = fa . p, beta = fb . p
-    double pg[2], pd[2];    // P's edge i from a_i along d_i: gamma(a_i), delta(a_i)
-    double prg[2], prd[2];  // 1 / gamma(d_i), 1 / delta(d_i)
-    double pc[2];           // a_i x d_i
-    double qa[2], qb[2];    // Q's edge j from b_j (about Q's centre) along e_j: alpha(b_j), beta(b_j)
-    double qra[2], qrb[2];  // 1 / alpha(e_j), 1 / beta(e_j)
-    double qc[2];           // b_j x e_j
-    double det23;           // p x e_0 = -det23 delta(p), p x e_1 = det23 gamma(p) (e_0 = u2, e_1 = u3)
-    double scale;           // 1 / (2 det01 det23)
+// Constants of the unit box spline of four directions.  P is the
+// parallelogram of the first two directions, Q that of the last two, each
+// about its centre with its pair turned counter-clockwise; frame coordinates
+// of a point x: (alpha, beta) in P's frame, (gamma, delta) in Q's, so that P
+// and Q are [-1/2, 1/2]^2 there.  Each parallelogram's edges come in mirror
+// pairs (edge i + 2 is edge i through the centre).  For P's edge a_i + t d_i
+// (and its mirror) with Q about p, |gamma| <= 1/2 holds for t in
+// [K + lg, K + ug] (mirror: [-K + lg, -K + ug]) with K = kg . p, and the same
+// for delta; for Q's edge p + b_j + t e_j the range is [-A + la, -A + ua]
+// (mirror: [A + la, A + ua]) with A = ka . p.  An edge's part inside the
+// other parallelogram adds (t1 - t0) (start x direction) to twice the area.
+struct A3Beta {
+    double kg[2][2], kd[2][2], lg[2], ug[2], ld[2], ud[2], pc[2];  // P's edge pairs
+    double ka[2][2], kb[2][2], la[2], ua[2], lb[2], ub[2], qc[2];  // Q's edge pairs
+    double xe[2][2];          // p x e_j = xe[j] . p
+    double scale;             // 1 / (2 det01 det23)
     // the support: |n_k . p| < h_k, n_k normal to u_k, h_k = (1/2) sum_j |n_k . u_j|
     double ny[4], h[4], rnx[4];  // rnx = 1 / n_k.x (0 when n_k.x = 0)
     double ex, ey;               // half the sums of |dx| and of |dy|
+    int ok;                      // 0 when two directions are parallel
 };
+
+__host__ __device__ constexpr double a3_abs(double v) { return v < 0 ? -v : v; }
+__host__ __device__ constexpr double a3_min(double a, double b) { return a < b ? a : b; }
+__host__ __device__ constexpr double a3_max(double a, double b) { return a < b ? b : a; }
+
+__host__ __device__ constexpr A3Beta make_beta(int x0, int y0, int x1, int y1, int x2, int y2, int x3, int y3) {
+    A3Beta G{};
+    const int dx[4] = {x0, x1, x2, x3}, dy[4] = {y0, y1, y2, y3};
+    double u[4][2] = {{(double)x0, (double)y0}, {(double)x1, (double)y1}, {(double)x2, (double)y2},
+                      {(double)x3, (double)y3}};
+    for (int pr = 0; pr < 2; ++pr) {
+        const double det = u[2 * pr][0] * u[2 * pr + 1][1] - u[2 * pr][1] * u[2 * pr + 1][0];
+        if (det == 0.0) return G;
+        if (det < 0.0)
+            for (int c = 0; c < 2; ++c) {
+                const double t = u[2 * pr][c];
+                u[2 * pr][c] = u[2 * pr + 1][c];
+                u[2 * pr + 1][c] = t;
+            }
+    }
+    const double det01 = u[0][0] * u[1][1] - u[0][1] * u[1][0];
+    const double det23 = u[2][0] * u[3][1] - u[2][1] * u[3][0];
+    // alpha = fa . x = (x ^ u1) / det01, beta = (u0 ^ x) / det01, gamma = (x ^ u3) / det23, delta = (u2 ^ x) / det23
+    const double fa[2] = {u[1][1] / det01, -u[1][0] / det01}, fb[2] = {-u[0][1] / det01, u[0][0] / det01};
+    const double fg[2] = {u[3][1] / det23, -u[3][0] / det23}, fd[2] = {-u[2][1] / det23, u[2][0] / det23};
+    // edges 0 and 1: from corner (-1/2, -1/2) along +v0, from (+1/2, -1/2) along +v1
+    const double sg[2][2] = {{-0.5, -0.5}, {0.5, -0.5}}, sd[2][2] = {{1, 0}, {0, 1}};
+    for (int i = 0; i < 2; ++i) {
+        for (int side = 0; side < 2; ++side) {
+            const double *v0 = u[2 * side], *v1 = u[2 * side + 1];
+            const double a[2] = {sg[i][0] * v0[0] + sg[i][1] * v1[0], sg[i][0] * v0[1] + sg[i][1] * v1[1]};
+            const double d[2] = {sd[i][0] * v0[0] + sd[i][1] * v1[0], sd[i][0] * v0[1] + sd[i][1] * v1[1]};
+            // the other parallelogram's two frame coordinates
+            const double *f1 = side == 0 ? fg : fa, *f2 = side == 0 ? fd : fb;
+            const double c1 = f1[0] * a[0] + f1[1] * a[1], c2 = f2[0] * a[0] + f2[1] * a[1];
+            const double e1 = f1[0] * d[0] + f1[1] * d[1], e2 = f2[0] * d[0] + f2[1] * d[1];
+            if (e1 == 0.0 || e2 == 0.0) return G;  // an edge of one parallel to an edge of the other
+            const double r1 = 1.0 / e1, r2 = 1.0 / e2;
+            const double lo1 = a3_min((-0.5 - c1) * r1, (0.5 - c1) * r1), hi1 = a3_max((-0.5 - c1) * r1, (0.5 - c1) * r1);
+            const double lo2 = a3_min((-0.5 - c2) * r2, (0.5 - c2) * r2), hi2 = a3_max((-0.5 - c2) * r2, (0.5 - c2) * r2);
+            const double cr = a[0] * d[1] - a[1] * d[0];
+            if (side == 0) {
+                G.kg[i][0] = fg[0] * r1;
+                G.kg[i][1] = fg[1] * r1;
+                G.kd[i][0] = fd[0] * r2;
+                G.kd[i][1] = fd[1] * r2;
+                G.lg[i] = lo1;
+                G.ug[i] = hi1;
+                G.ld[i] = lo2;
+                G.ud[i] = hi2;
+                G.pc[i] = cr;
+            } else {
+                G.ka[i][0] = fa[0] * r1;
+                G.ka[i][1] = fa[1] * r1;
+                G.kb[i][0] = fb[0] * r2;
+                G.kb[i][1] = fb[1] * r2;
+                G.la[i] = lo1;
+                G.ua[i] = hi1;
+                G.lb[i] = lo2;
+                G.ub[i] = hi2;
+                G.qc[i] = cr;
+                // p x d = p.x d.y - p.y d.x
+                G.xe[i][0] = d[1];
+                G.xe[i][1] = -d[0];
+            }
+        }
+    }
+    G.scale = 0.5 / (det01 * det23);
+    for (int k = 0; k < 4; ++k) {
+        G.ex += 0.5 * a3_abs(dx[k]);
+        G.ey += 0.5 * a3_abs(dy[k]);
+        const double nx = -dy[k], ny = dx[k];
+        double h = 0.0;
+        for (int j = 0; j < 4; ++j) h += 0.5 * a3_abs(nx * dx[j] + ny * dy[j]);
+        G.ny[k] = ny;
+        G.h[k] = h;
+        G.rnx[k] = nx != 0.0 ? 1.0 / nx : 0.0;
+    }
+    G.ok = 1;
+    return G;
+}
+
+// The direction sets with constants built into the kernels: 1 for those of
+// Alg. 3 and Table 1 (canonical sign), 2 for those of Section 1.1; 0 reads
+// them from the launch arguments.
+__host__ __device__ constexpr A3Beta beta_of_set(int set) {
+    return set == 1 ? make_beta(2, 1, 1, 2, 1, -2, 2, -1) : make_beta(1, 0, 0, 1, 1, 1, 1, -1);
+}
 
 struct A3Args {
     const void *img;
@@ -88,37 +177,22 @@ struct A3Args {
     int dx[4], dy[4];
     float max_step;
     int64_t tiles_x, tiles;
-    A3Geom g;
+    A3Beta g;  // for other direction sets
 };
 
-// Narrow [t0, t1] to the t with |v + t dv| <= 1/2 (r = 1 / dv, dv != 0).
-__device__ __forceinline__ void slab(double v, double r, double &t0, double &t1) {
-    const double ta = (-0.5 - v) * r, tb = (0.5 - v) * r;
-    t0 = fmax(t0, fmin(ta, tb));
-    t1 = fmin(t1, fmax(ta, tb));
-}
-
 // beta_b(p): the overlap of P (about 0) and Q (about p), over |P| |Q|.
-__device__ __forceinline__ double unit_box_spline(const A3Geom &G, double px, double py) {
-    const double gp = G.fg[0] * px + G.fg[1] * py, dp = G.fd[0] * px + G.fd[1] * py;
-    const double ap = G.fa[0] * px + G.fa[1] * py, bp = G.fb[0] * px + G.fb[1] * py;
+__device__ __forceinline__ double unit_box_spline(const A3Beta &G, double px, double py) {
     double twice = 0.0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        // P's edge i and its mirror, in Q's frame about p
-        double t0 = 0.0, t1 = 1.0, m0 = 0.0, m1 = 1.0;
-        slab(G.pg[i] - gp, G.prg[i], t0, t1);
-        slab(G.pd[i] - dp, G.prd[i], t0, t1);
-        slab(-G.pg[i] - gp, -G.prg[i], m0, m1);
-        slab(-G.pd[i] - dp, -G.prd[i], m0, m1);
+        const double K = G.kg[i][0] * px + G.kg[i][1] * py, J = G.kd[i][0] * px + G.kd[i][1] * py;
+        const double t0 = fmax(fmax(K + G.lg[i], J + G.ld[i]), 0.0), t1 = fmin(fmin(K + G.ug[i], J + G.ud[i]), 1.0);
+        const double m0 = fmax(fmax(G.lg[i] - K, G.ld[i] - J), 0.0), m1 = fmin(fmin(G.ug[i] - K, G.ud[i] - J), 1.0);
         twice += (fmax(t1 - t0, 0.0) + fmax(m1 - m0, 0.0)) * G.pc[i];
-        // Q's edge i and its mirror, in P's frame
-        double s0 = 0.0, s1 = 1.0, n0 = 0.0, n1 = 1.0;
-        slab(G.qa[i] + ap, G.qra[i], s0, s1);
-        slab(G.qb[i] + bp, G.qrb[i], s0, s1);
-        slab(-G.qa[i] + ap, -G.qra[i], n0, n1);
-        slab(-G.qb[i] + bp, -G.qrb[i], n0, n1);
-        const double pe = i == 0 ? -G.det23 * dp : G.det23 * gp;  // p x e_i
+        const double A = G.ka[i][0] * px + G.ka[i][1] * py, B = G.kb[i][0] * px + G.kb[i][1] * py;
+        const double s0 = fmax(fmax(G.la[i] - A, G.lb[i] - B), 0.0), s1 = fmin(fmin(G.ua[i] - A, G.ub[i] - B), 1.0);
+        const double n0 = fmax(fmax(G.la[i] + A, G.lb[i] + B), 0.0), n1 = fmin(fmin(G.ua[i] + A, G.ub[i] + B), 1.0);
+        const double pe = G.xe[i][0] * px + G.xe[i][1] * py;
         twice += fmax(s1 - s0, 0.0) * (G.qc[i] + pe) + fmax(n1 - n0, 0.0) * (G.qc[i] - pe);
     }
     return twice * G.scale;
@@ -161,7 +235,7 @@ struct A3Shared {
 // at the lattice points of beta_b's support around q, row by row (the
 // support's cross-section at each row bounds the columns), weighted by
 // beta_b(q - m).  (ox, oy) is the pixel inside the WX x WY rectangle.
-__device__ __forceinline__ double interpolate(const A3Geom &G, const double *win, int WX, int WY, int ox, int oy,
+__device__ __forceinline__ double interpolate(const A3Beta &G, const double *win, int WX, int WY, int ox, int oy,
                                               double qx, double qy) {
     const int mx0 = (int)ceil(qx - G.ex), mx1 = (int)floor(qx + G.ex);
     const int my0 = (int)ceil(qy - G.ey), my1 = (int)floor(qy + G.ey);
@@ -195,12 +269,12 @@ __device__ __forceinline__ double interpolate(const A3Geom &G, const double *win
 // One tile: the rectangle of every piece of it that fits `cap` window
 // elements, at pieces of at least b_min pixels a side; a tile that fits no
 // such piece goes to q_out (NULL in the last tier, whose buffer fits one pixel).
-__device__ void a3_tile(const A3Args &a, int64_t tile, int cap, int b_min, int32_t *q_out, int32_t *n_out,
-                        double *win, A3Shared &sh, bool &nonfinite) {
+__device__ __forceinline__ void a3_tile_body(const A3Args &a, const A3Beta &G, int64_t tile, int cap, int b_min,
+                                             int32_t *q_out, int32_t *n_out, double *win, A3Shared &sh,
+                                             bool &nonfinite) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t x0 = (tile % a.tiles_x) * kA3Tile, y0 = (tile / a.tiles_x) * kA3Tile;
     const int64_t HW = a.H * a.W;
-    const A3Geom &G = a.g;
 
     // 1. each pixel's steps and the offsets of the lattice points its taps read
     Ext e{INT_MAX, INT_MIN, INT_MAX, INT_MIN};
@@ -344,6 +418,18 @@ __device__ void a3_tile(const A3Args &a, int64_t tile, int cap, int b_min, int32
     __syncthreads();  // the shared words are free for the next tile
 }
 
+// SET 1 and 2 build the constants of their direction set into the code.
+template <int SET>
+__device__ __forceinline__ void a3_tile(const A3Args &a, int64_t tile, int cap, int b_min, int32_t *q_out,
+                                        int32_t *n_out, double *win, A3Shared &sh, bool &nonfinite) {
+    if constexpr (SET == 0) {
+        a3_tile_body(a, a.g, tile, cap, b_min, q_out, n_out, win, sh, nonfinite);
+    } else {
+        constexpr A3Beta G = beta_of_set(SET);
+        a3_tile_body(a, G, tile, cap, b_min, q_out, n_out, win, sh, nonfinite);
+    }
+}
+
 __global__ void k_alg3_begin(int32_t *status) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         status[ST_A3_QUEUED0] = 0;
@@ -356,90 +442,74 @@ __device__ __forceinline__ void flag_nonfinite(const A3Args &a, bool nonfinite) 
 }
 
 // First tier: one block per tile, in XCD order.
+template <int SET>
 __global__ __launch_bounds__(kA3Threads) void k_alg3_tiles(A3Args a, int cap, int b_min, int32_t *q_out,
                                                            int32_t *n_out) {
     extern __shared__ double win[];
     __shared__ A3Shared sh;
     const int64_t tile = xcd_item(blockIdx.x, a.tiles);
     bool nonfinite = false;
-    if (tile < a.tiles) a3_tile(a, tile, cap, b_min, q_out, n_out, win, sh, nonfinite);
+    if (tile < a.tiles) a3_tile<SET>(a, tile, cap, b_min, q_out, n_out, win, sh, nonfinite);
     flag_nonfinite(a, nonfinite);
 }
 
 // Later tiers: blocks work through the tiles the previous tier queued.
+template <int SET>
 __global__ __launch_bounds__(kA3Threads) void k_alg3_queue(A3Args a, int cap, int b_min, const int32_t *q_in,
                                                            const int32_t *n_in, int32_t *q_out, int32_t *n_out) {
     extern __shared__ double win[];
     __shared__ A3Shared sh;
     const int n = *n_in;
     bool nonfinite = false;
-    for (int i = blockIdx.x; i < n; i += gridDim.x) a3_tile(a, q_in[i], cap, b_min, q_out, n_out, win, sh, nonfinite);
+    for (int i = blockIdx.x; i < n; i += gridDim.x) a3_tile<SET>(a, q_in[i], cap, b_min, q_out, n_out, win, sh, nonfinite);
     flag_nonfinite(a, nonfinite);
 }
 
-// Host: the constants of beta_b for four directions (the first two span P, the
-// last two Q; each pair turned counter-clockwise).
-bsf_status make_a3_geom(const int dx[4], const int dy[4], A3Geom *G) {
-    double u[4][2];
-    for (int k = 0; k < 4; ++k) {
-        u[k][0] = dx[k];
-        u[k][1] = dy[k];
+// The launch tiers for a plan: buffer sizes in window elements, the last one
+// holding any single pixel's rectangle (and a whole tile's when it is small).
+struct A3Tiers {
+    int n;
+    int cap[3];
+};
+
+// Which direction set's constants are built in (0: none).
+int a3_set(const Plan &p) {
+    const int sets[2][8] = {{2, 1, 1, 2, 1, -2, 2, -1}, {1, 0, 0, 1, 1, 1, 1, -1}};
+    for (int k = 0; k < 2; ++k) {
+        int found = 0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+                if (p.dx[i] == sets[k][2 * j] && p.dy[i] == sets[k][2 * j + 1]) ++found;
+        if (found == 4) return k + 1;
     }
-    for (int pair = 0; pair < 2; ++pair) {
-        double *v0 = u[2 * pair], *v1 = u[2 * pair + 1];
-        const double det = v0[0] * v1[1] - v0[1] * v1[0];
-        if (det == 0.0) return BSF_E_INVALID;
-        if (det < 0.0)
-            for (int c = 0; c < 2; ++c) std::swap(v0[c], v1[c]);
+    return 0;
+}
+
+template <int SET>
+bsf_status a3_launch(const A3Args &a, const A3Tiers &tiers, int32_t *const queue[2], int32_t *const queued[2],
+                     hipStream_t st) {
+    static bool s_big_lds = false;  // allow the largest buffer, once per process
+    if (!s_big_lds) {
+        for (const void *k : {reinterpret_cast<const void *>(k_alg3_tiles<SET>),
+                              reinterpret_cast<const void *>(k_alg3_queue<SET>)})
+            BSF_HIP_CHECK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)(kA3CapMax * sizeof(double))));
+        s_big_lds = true;
     }
-    auto cr = [](const double *a, const double *b) { return a[0] * b[1] - a[1] * b[0]; };
-    const double det01 = cr(u[0], u[1]), det23 = cr(u[2], u[3]);
-    // p x v = p.x v.y - p.y v.x; v x p = v.x p.y - v.y p.x
-    G->fg[0] = u[3][1] / det23;
-    G->fg[1] = -u[3][0] / det23;
-    G->fd[0] = -u[2][1] / det23;
-    G->fd[1] = u[2][0] / det23;
-    G->fa[0] = u[1][1] / det01;
-    G->fa[1] = -u[1][0] / det01;
-    G->fb[0] = -u[0][1] / det01;
-    G->fb[1] = u[0][0] / det01;
-    auto frame = [](const double f[2], const double *v) { return f[0] * v[0] + f[1] * v[1]; };
-    // edges 0 and 1 of each parallelogram: from (-,-) along +v0, from (+,-) along +v1
-    const double sg[2][2] = {{-0.5, -0.5}, {0.5, -0.5}};
-    const double sd[2][2] = {{1, 0}, {0, 1}};
-    for (int i = 0; i < 2; ++i) {
-        const double a[2] = {sg[i][0] * u[0][0] + sg[i][1] * u[1][0], sg[i][0] * u[0][1] + sg[i][1] * u[1][1]};
-        const double d[2] = {sd[i][0] * u[0][0] + sd[i][1] * u[1][0], sd[i][0] * u[0][1] + sd[i][1] * u[1][1]};
-        G->pg[i] = frame(G->fg, a);
-        G->pd[i] = frame(G->fd, a);
-        const double gd = frame(G->fg, d), dd = frame(G->fd, d);
-        if (gd == 0.0 || dd == 0.0) return BSF_E_INVALID;  // an edge of P parallel to one of Q
-        G->prg[i] = 1.0 / gd;
-        G->prd[i] = 1.0 / dd;
-        G->pc[i] = cr(a, d);
-        const double b[2] = {sg[i][0] * u[2][0] + sg[i][1] * u[3][0], sg[i][0] * u[2][1] + sg[i][1] * u[3][1]};
-        const double e[2] = {sd[i][0] * u[2][0] + sd[i][1] * u[3][0], sd[i][0] * u[2][1] + sd[i][1] * u[3][1]};
-        G->qa[i] = frame(G->fa, b);
-        G->qb[i] = frame(G->fb, b);
-        const double ad = frame(G->fa, e), bd = frame(G->fb, e);
-        if (ad == 0.0 || bd == 0.0) return BSF_E_INVALID;
-        G->qra[i] = 1.0 / ad;
-        G->qrb[i] = 1.0 / bd;
-        G->qc[i] = cr(b, e);
-    }
-    G->det23 = det23;
-    G->scale = 0.5 / (det01 * det23);
-    G->ex = 0.0;
-    G->ey = 0.0;
-    for (int k = 0; k < 4; ++k) {
-        G->ex += 0.5 * std::abs(dx[k]);
-        G->ey += 0.5 * std::abs(dy[k]);
-        const double nx = -dy[k], ny = dx[k];
-        double h = 0.0;
-        for (int j = 0; j < 4; ++j) h += 0.5 * std::fabs(nx * dx[j] + ny * dy[j]);
-        G->ny[k] = ny;
-        G->h[k] = h;
-        G->rnx[k] = nx != 0.0 ? 1.0 / nx : 0.0;
+    for (int i = 0; i < tiers.n; ++i) {
+        const bool last = i == tiers.n - 1;
+        const int cap = tiers.cap[i], b_min = last ? 1 : kA3MinPiece;
+        int32_t *q_out = last ? nullptr : queue[i % 2], *n_out = last ? nullptr : queued[i % 2];
+        const size_t lds = (size_t)cap * sizeof(double);
+        if (i == 0) {
+            hipLaunchKernelGGL(k_alg3_tiles<SET>, dim3((unsigned)xcd_grid(a.tiles)), dim3(kA3Threads), lds, st, a,
+                               cap, b_min, q_out, n_out);
+        } else {
+            const unsigned grid = (unsigned)std::min<int64_t>(a.tiles, 2048);
+            hipLaunchKernelGGL(k_alg3_queue<SET>, dim3(grid), dim3(kA3Threads), lds, st, a, cap, b_min,
+                               queue[(i - 1) % 2], queued[(i - 1) % 2], q_out, n_out);
+        }
+        BSF_HIP_CHECK(hipGetLastError());
     }
     return BSF_OK;
 }
@@ -455,13 +525,6 @@ int64_t a3_window(const Plan &p, int b) {
     const double S = p.max_step;
     return (b + (int64_t)floor(S * sx) + sx) * (b + (int64_t)floor(S * sy) + sy);
 }
-
-// The launch tiers for a plan: buffer sizes in window elements, the last one
-// holding any single pixel's rectangle (and a whole tile's when it is small).
-struct A3Tiers {
-    int n;
-    int cap[3];
-};
 
 bsf_status a3_check(const bsf_config *cfg, int64_t H, int64_t W, Plan &p, A3Tiers &t) {
     bsf_status r = make_plan(cfg, H, W, &p);
@@ -521,39 +584,22 @@ bsf_status bsf_filter_alg3(const bsf_config *cfg, bsf_dtype dtype, const void *i
         a.dy[k] = p.dy[k];
     }
     a.max_step = p.max_step;
-    r = make_a3_geom(a.dx, a.dy, &a.g);
-    if (r != BSF_OK) return r;
+    a.g = make_beta(p.dx[0], p.dy[0], p.dx[1], p.dy[1], p.dx[2], p.dy[2], p.dx[3], p.dy[3]);
+    if (!a.g.ok) return BSF_E_INVALID;
     a.tiles_x = (W + kA3Tile - 1) / kA3Tile;
     a.tiles = a.tiles_x * ((H + kA3Tile - 1) / kA3Tile);
-    int32_t *queue[2] = {reinterpret_cast<int32_t *>(static_cast<char *>(ws) + kStatusBytes),
-                         reinterpret_cast<int32_t *>(static_cast<char *>(ws) + kStatusBytes + a3_queue_bytes(a.tiles))};
-    int32_t *queued[2] = {a.status + ST_A3_QUEUED0, a.status + ST_A3_QUEUED1};
+    int32_t *const queue[2] = {reinterpret_cast<int32_t *>(static_cast<char *>(ws) + kStatusBytes),
+                               reinterpret_cast<int32_t *>(static_cast<char *>(ws) + kStatusBytes +
+                                                           a3_queue_bytes(a.tiles))};
+    int32_t *const queued[2] = {a.status + ST_A3_QUEUED0, a.status + ST_A3_QUEUED1};
     hipStream_t st = static_cast<hipStream_t>(stream);
-    static bool s_big_lds = false;  // allow the largest buffer once per process
-    if (!s_big_lds) {
-        for (const void *k : {reinterpret_cast<const void *>(k_alg3_tiles), reinterpret_cast<const void *>(k_alg3_queue)})
-            BSF_HIP_CHECK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                              (int)(kA3CapMax * sizeof(double))));
-        s_big_lds = true;
-    }
     hipLaunchKernelGGL(k_alg3_begin, dim3(1), dim3(64), 0, st, a.status);
     BSF_HIP_CHECK(hipGetLastError());
-    for (int i = 0; i < tiers.n; ++i) {
-        const bool last = i == tiers.n - 1;
-        const int cap = tiers.cap[i], b_min = last ? 1 : kA3MinPiece;
-        int32_t *q_out = last ? nullptr : queue[i % 2], *n_out = last ? nullptr : queued[i % 2];
-        const size_t lds = (size_t)cap * sizeof(double);
-        if (i == 0) {
-            hipLaunchKernelGGL(k_alg3_tiles, dim3((unsigned)xcd_grid(a.tiles)), dim3(kA3Threads), lds, st, a, cap,
-                               b_min, q_out, n_out);
-        } else {
-            const unsigned grid = (unsigned)std::min<int64_t>(a.tiles, 2048);
-            hipLaunchKernelGGL(k_alg3_queue, dim3(grid), dim3(kA3Threads), lds, st, a, cap, b_min,
-                               queue[(i - 1) % 2], queued[(i - 1) % 2], q_out, n_out);
-        }
-        BSF_HIP_CHECK(hipGetLastError());
+    switch (a3_set(p)) {
+    case 1: return a3_launch<1>(a, tiers, queue, queued, st);
+    case 2: return a3_launch<2>(a, tiers, queue, queued, st);
+    default: return a3_launch<0>(a, tiers, queue, queued, st);
     }
-    return BSF_OK;
 }
 
 }  // extern "C"
