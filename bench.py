@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--int-steps", type=int, default=20)
     ap.add_argument("--diff-images", type=int, default=16, help="images of the differentiation workload (0: skip)")
     ap.add_argument("--diff-steps", type=int, default=3)
+    ap.add_argument("--alg3-size", type=int, default=4096, help="Alg. 3 workload side (0: skip)")
+    ap.add_argument("--alg3-steps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, one device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -264,6 +266,49 @@ def main():
         log("differentiation %d x %dx%d fwd+adjoint: %.3f ms" % (len(imgs5), H5, W5, ms5))
         del imgs5, steps5, gouts5, ws5, wsb5
 
+    # ---- Alg. 3: the box spline of Table 1 read through eq. interpolation,
+    # FP64, on a covariance field (minimum-kurtosis steps for that box spline)
+    alg3 = None
+    if args.alg3_size > 0:
+        da = WL.workload_alg3(args.alg3_size, args.alg3_size)
+        Ha, Wa = da["img"].shape
+        cfga = bsf.Config(dirs=da["dirs"], order=1, tied=True, mode=bsf.STEPS_REAL, max_step=da["max_step"])
+        imga = torch.from_numpy(da["img"]).to(dev)
+        stepsa = bsf.cov_to_steps(cfga, torch.from_numpy(da["cov"]).to(dev))
+        wsa = bsf.Workspace(bsf.lib().bsf_alg3_workspace_bytes(bsf.ctypes.byref(cfga.c()), Ha, Wa), dev)
+        outa = torch.empty((Ha, Wa), dtype=torch.float32, device=dev)
+        out64a = torch.empty((Ha, Wa), dtype=torch.float64, device=dev)
+        bsf.filter_alg3(cfga, imga, stepsa, out=outa, out_f64=out64a, ws=wsa)
+        torch.cuda.synchronize()
+        ta = []
+        for _ in range(args.alg3_steps):
+            e0.record(stream)
+            bsf.filter_alg3(cfga, imga, stepsa, out=outa, ws=wsa)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ta.append(e0.elapsed_time(e1))
+        msa = float(np.median(ta))
+        # sampled pixels against the oracle's Alg. 3 on crops holding each footprint
+        sa = stepsa.cpu().numpy()
+        o64 = out64a.cpu().numpy()
+        erra = 0.0
+        for x, y in rng.integers(0, [Wa, Ha], (16, 2)):
+            s_ = sa[:, y, x].astype(np.float64)
+            rx = int(np.ceil(0.5 * sum(abs(u[0]) * v for u, v in zip(da["dirs"], s_)))) + 3
+            ry = int(np.ceil(0.5 * sum(abs(u[1]) * v for u, v in zip(da["dirs"], s_)))) + 3
+            x0, x1, y0, y1 = max(0, x - rx), min(Wa, x + rx + 1), max(0, y - ry), min(Ha, y + ry + 1)
+            ref = O.alg3(np.ascontiguousarray(da["img"][y0:y1, x0:x1]), da["dirs"],
+                         np.ascontiguousarray(sa[:, y0:y1, x0:x1]),
+                         pix=np.array([(y - y0) * (x1 - x0) + (x - x0)]))[0]
+            erra = max(erra, abs(float(o64[y, x]) - ref))
+        flags_a, _, _ = wsa.status()
+        alg3 = {"workload": da["name"], "ms_per_step": msa, "value": Ha * Wa / (msa / 1e3) / 1e6,
+                "unit": "Mpixels/s", "dtype": "f64", "steps": args.alg3_steps,
+                "max_abs_err_vs_oracle": erra, "pixels_checked": 16, "device_flags": flags_a,
+                "step_percentiles_50_99_100": [float(v) for v in np.percentile(sa, [50, 99, 100])]}
+        log("alg3 %dx%d: %.3f ms, max abs err %.2e" % (Ha, Wa, msa, erra))
+        del imga, stepsa, wsa, outa, out64a
+
     # ---- integer steps on a uint8 image: exact int64 numerator and prod s
     integer = None
     if args.int_size > 0:
@@ -428,6 +473,7 @@ def main():
                 "minimum_gbs": minimum_bytes / (step_ms / 1e3) / 1e9,
                 "peak_gbs": HBM_PEAK_GBS},
         "differentiation": diff,
+        "alg3": alg3,
         "tuning": None if tuning is None else {k: tuning[k] for k in ("gather_wx", "line_tl", "box_h")},
     }
     print(json.dumps(res))

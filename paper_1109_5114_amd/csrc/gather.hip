@@ -874,27 +874,61 @@ __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__res
     if constexpr (I + 1 < cbox::kCombos) box_fwd_all<I + 1, S>(a, s_box, active, t, J);
 }
 
-__device__ __forceinline__ double contract81(const double Jd[81], const double w0[3], const double w1[3],
-                                             const double w2[3], const double w3[3]) {
-    double r = 0.0;
+// The value and the four step derivatives of the 81-term contraction in one
+// sweep over J, converting each sum to FP64 as it is consumed (no FP64
+// copy of J is ever held): S_L are the partial sums over the
+// directions from L on with the weights w, S_L^(k) the same with dw_k in
+// place of w_k.  Each result is the nested sum over o0 (outermost) to o3
+// (innermost) of the weights times J.
+template <bool DERIV, class GetJ>
+__device__ __forceinline__ void contract81_sweep(const GetJ &J, const double w[4][3], const double dw[4][3],
+                                                 double &out, double d[4]) {
+    double r = 0.0, r_0 = 0.0, r_1 = 0.0, r_2 = 0.0, r_3 = 0.0;
 #pragma unroll
     for (int o0 = 0; o0 < 3; ++o0) {
-        double r1 = 0.0;
+        double s1 = 0.0, s1_1 = 0.0, s1_2 = 0.0, s1_3 = 0.0;
 #pragma unroll
         for (int o1 = 0; o1 < 3; ++o1) {
-            double r2 = 0.0;
+            double s2 = 0.0, s2_2 = 0.0, s2_3 = 0.0;
 #pragma unroll
             for (int o2 = 0; o2 < 3; ++o2) {
-                double r3 = 0.0;
+                double s3 = 0.0, s3_3 = 0.0;
 #pragma unroll
-                for (int o3 = 0; o3 < 3; ++o3) r3 += w3[o3] * Jd[cbox::jidx(o0, o1, o2, o3)];
-                r2 += w2[o2] * r3;
+                for (int o3 = 0; o3 < 3; ++o3) {
+                    const double j = -(double)(int64_t)J(cbox::jidx(o0, o1, o2, o3));
+                    s3 += w[3][o3] * j;
+                    if (DERIV) s3_3 += dw[3][o3] * j;
+                }
+                s2 += w[2][o2] * s3;
+                if (DERIV) {
+                    s2_2 += dw[2][o2] * s3;
+                    s2_3 += w[2][o2] * s3_3;
+                }
             }
-            r1 += w1[o1] * r2;
+            s1 += w[1][o1] * s2;
+            if (DERIV) {
+                s1_1 += dw[1][o1] * s2;
+                s1_2 += w[1][o1] * s2_2;
+                s1_3 += w[1][o1] * s2_3;
+            }
         }
-        r += w0[o0] * r1;
+        r += w[0][o0] * s1;
+        if (DERIV) {
+            r_0 += dw[0][o0] * s1;
+            r_1 += w[0][o0] * s1_1;
+            r_2 += w[0][o0] * s1_2;
+            r_3 += w[0][o0] * s1_3;
+        }
+        // the next third of J is not touched before this one is consumed
+        __builtin_amdgcn_sched_barrier(0);
     }
-    return r;
+    out = r;
+    if (DERIV) {
+        d[0] = r_0;
+        d[1] = r_1;
+        d[2] = r_2;
+        d[3] = r_3;
+    }
 }
 
 // Tile-wide min / max of R per direction over the active pixels.
@@ -985,6 +1019,15 @@ __global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     box_fwd_all<0, S>(a, s_box, active, t, J);
+    // The last kPark sums wait in the box buffers, idle now (the last
+    // combination ended with a barrier), so that the epilogue's own values fit
+    // in registers beside the rest; each thread reads back only its own.
+    constexpr int kPark = 36, kKeep = 81 - kPark, kThreads = 64 * S::Waves;
+    static_assert(kPark * kThreads <= 2 * S::Elems, "parking space");
+    uint64_t *__restrict__ park = s_box + threadIdx.x;
+#pragma unroll
+    for (int q = kKeep; q < 81; ++q) park[(q - kKeep) * kThreads] = J[q];
+    const auto getJ = [&](int q) -> uint64_t { return q < kKeep ? J[q] : park[(q - kKeep) * kThreads]; };
     // the pixel's position and phases are formed again here rather than held
     // through the loop
     const int px = t.x_lo + fwd_tx(threadIdx.x), py = t.y_lo + fwd_ty(threadIdx.x);
@@ -1000,21 +1043,17 @@ __global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box
         sk[k] = s;
         den *= (double)s * (double)s;
     }
-    double Jd[81];
-#pragma unroll
-    for (int q = 0; q < 81; ++q) Jd[q] = -(double)(int64_t)J[q];
     double w[4][3], dw[4][3];
 #pragma unroll
     for (int k = 0; k < 4; ++k) phase_weights(ph[k], w[k], dw[k]);
     const int F = a.status[ST_F_USED];
-    const double outv = ldexp_neg(contract81(Jd, w[0], w[1], w[2], w[3]), F) / den;
+    // one sweep for the value and the derivatives alike: two specialised
+    // sweeps would share, and hoist above their branch, every conversion of J
+    double r, d[4];
+    contract81_sweep<true>(getJ, w, dw, r, d);
+    const double outv = ldexp_neg(r, F) / den;
     if (a.out) a.out[idx] = (float)outv;
     if (a.dsteps) {
-        double d[4];
-        d[0] = contract81(Jd, dw[0], w[1], w[2], w[3]);
-        d[1] = contract81(Jd, w[0], dw[1], w[2], w[3]);
-        d[2] = contract81(Jd, w[0], w[1], dw[2], w[3]);
-        d[3] = contract81(Jd, w[0], w[1], w[2], dw[3]);
         // d phi / d s = 1/2, and each step enters prod s twice
 #pragma unroll
         for (int k = 0; k < 4; ++k)
