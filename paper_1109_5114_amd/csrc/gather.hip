@@ -874,61 +874,61 @@ __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__res
     if constexpr (I + 1 < cbox::kCombos) box_fwd_all<I + 1, S>(a, s_box, active, t, J);
 }
 
-// The value and the four step derivatives of the 81-term contraction in one
-// sweep over J, converting each sum to FP64 as it is consumed (no FP64
-// copy of J is ever held): S_L are the partial sums over the
-// directions from L on with the weights w, S_L^(k) the same with dw_k in
-// place of w_k.  Each result is the nested sum over o0 (outermost) to o3
-// (innermost) of the weights times J.
-template <bool DERIV, class GetJ>
-__device__ __forceinline__ void contract81_sweep(const GetJ &J, const double w[4][3], const double dw[4][3],
-                                                 double &out, double d[4]) {
-    double r = 0.0, r_0 = 0.0, r_1 = 0.0, r_2 = 0.0, r_3 = 0.0;
+// The 81-term contraction of J with the phase weights: the value (weights w
+// for every direction) and, with DA / DB set, the derivatives with dw_A / dw_B
+// in place of w_A / w_B, in one sweep over J that converts each sum to FP64
+// as it is consumed (no FP64 copy of J is ever held).  S_L are the partial
+// sums over the directions from L on; every result is the nested sum over o0
+// (outermost) to o3 (innermost) of the weights times J.  The value and four
+// derivatives together need more registers than a wavefront has beside J, so
+// a pixel takes two sweeps of two results each (and the value).
+template <int DA, int DB, int KEEP, int THREADS>
+__device__ __forceinline__ void contract81_sweep(const uint64_t Jr[81], const uint64_t *park, const double w[4][3],
+                                                 const double dw[4][3], double &out, double &dA, double &dB) {
+    constexpr bool A = DA >= 0, B = DB >= 0;
+    // weights of level L: plain, or the derivative's where L is its direction
+    auto wt = [&](int which, int L, int o) -> double { return which == L ? dw[L][o] : w[L][o]; };
+    double r = 0.0, ra = 0.0, rb = 0.0;
 #pragma unroll
     for (int o0 = 0; o0 < 3; ++o0) {
-        double s1 = 0.0, s1_1 = 0.0, s1_2 = 0.0, s1_3 = 0.0;
+        // sums J[q], q >= KEEP, wait in LDS at park[(q - KEEP) * THREADS + thread]: the
+        // index is formed afresh for each third, so that fewer of their loads
+        // are hoisted ahead of the sums before them (the registers would not
+        // hold them all)
+        int own = (int)threadIdx.x;
+        asm volatile("" : "+v"(own));
+        const auto J = [&](int q) -> uint64_t { return q < KEEP ? Jr[q] : park[(q - KEEP) * THREADS + own]; };
+        double s1 = 0.0, s1a = 0.0, s1b = 0.0;
 #pragma unroll
         for (int o1 = 0; o1 < 3; ++o1) {
-            double s2 = 0.0, s2_2 = 0.0, s2_3 = 0.0;
+            double s2 = 0.0, s2a = 0.0, s2b = 0.0;
 #pragma unroll
             for (int o2 = 0; o2 < 3; ++o2) {
-                double s3 = 0.0, s3_3 = 0.0;
+                double s3 = 0.0, s3a = 0.0, s3b = 0.0;
 #pragma unroll
                 for (int o3 = 0; o3 < 3; ++o3) {
                     const double j = -(double)(int64_t)J(cbox::jidx(o0, o1, o2, o3));
                     s3 += w[3][o3] * j;
-                    if (DERIV) s3_3 += dw[3][o3] * j;
+                    if (A) s3a += wt(DA, 3, o3) * j;
+                    if (B) s3b += wt(DB, 3, o3) * j;
                 }
                 s2 += w[2][o2] * s3;
-                if (DERIV) {
-                    s2_2 += dw[2][o2] * s3;
-                    s2_3 += w[2][o2] * s3_3;
-                }
+                if (A) s2a += wt(DA, 2, o2) * (DA == 3 ? s3a : s3);
+                if (B) s2b += wt(DB, 2, o2) * (DB == 3 ? s3b : s3);
             }
             s1 += w[1][o1] * s2;
-            if (DERIV) {
-                s1_1 += dw[1][o1] * s2;
-                s1_2 += w[1][o1] * s2_2;
-                s1_3 += w[1][o1] * s2_3;
-            }
+            if (A) s1a += wt(DA, 1, o1) * (DA >= 2 ? s2a : s2);
+            if (B) s1b += wt(DB, 1, o1) * (DB >= 2 ? s2b : s2);
         }
         r += w[0][o0] * s1;
-        if (DERIV) {
-            r_0 += dw[0][o0] * s1;
-            r_1 += w[0][o0] * s1_1;
-            r_2 += w[0][o0] * s1_2;
-            r_3 += w[0][o0] * s1_3;
-        }
+        if (A) ra += wt(DA, 0, o0) * (DA >= 1 ? s1a : s1);
+        if (B) rb += wt(DB, 0, o0) * (DB >= 1 ? s1b : s1);
         // the next third of J is not touched before this one is consumed
         __builtin_amdgcn_sched_barrier(0);
     }
     out = r;
-    if (DERIV) {
-        d[0] = r_0;
-        d[1] = r_1;
-        d[2] = r_2;
-        d[3] = r_3;
-    }
+    dA = ra;
+    dB = rb;
 }
 
 // Tile-wide min / max of R per direction over the active pixels.
@@ -969,7 +969,9 @@ __device__ __forceinline__ void tile_R_range(const int R[4], bool active, int Rl
     }
 }
 
-template <bool BATCH, int TH>
+// DERIV: the call asks for the step derivatives (their sweeps need registers
+// the value alone does not, so the kernel without them is its own instance).
+template <bool BATCH, int TH, bool DERIV>
 __global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box(
     GatherArgs one, const GatherArgs *__restrict__ table, const int64_t *__restrict__ prefix, int B) {
     using S = FwdShape<TH>;
@@ -1024,10 +1026,8 @@ __global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box
     // in registers beside the rest; each thread reads back only its own.
     constexpr int kPark = 36, kKeep = 81 - kPark, kThreads = 64 * S::Waves;
     static_assert(kPark * kThreads <= 2 * S::Elems, "parking space");
-    uint64_t *__restrict__ park = s_box + threadIdx.x;
 #pragma unroll
-    for (int q = kKeep; q < 81; ++q) park[(q - kKeep) * kThreads] = J[q];
-    const auto getJ = [&](int q) -> uint64_t { return q < kKeep ? J[q] : park[(q - kKeep) * kThreads]; };
+    for (int q = kKeep; q < 81; ++q) s_box[(q - kKeep) * kThreads + threadIdx.x] = J[q];
     // the pixel's position and phases are formed again here rather than held
     // through the loop
     const int px = t.x_lo + fwd_tx(threadIdx.x), py = t.y_lo + fwd_ty(threadIdx.x);
@@ -1043,17 +1043,34 @@ __global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box
         sk[k] = s;
         den *= (double)s * (double)s;
     }
-    double w[4][3], dw[4][3];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) phase_weights(ph[k], w[k], dw[k]);
     const int F = a.status[ST_F_USED];
-    // one sweep for the value and the derivatives alike: two specialised
-    // sweeps would share, and hoist above their branch, every conversion of J
-    double r, d[4];
-    contract81_sweep<true>(getJ, w, dw, r, d);
+    // With the derivatives: two sweeps of two derivatives each (directions 0
+    // and 1, then 2 and 3; the first also forms the value).  The second reads
+    // J and the phases afresh (registers laundered, the parked sums re-read),
+    // so that neither its weights nor any conversion of the first are held
+    // across the first.  Both epilogues fit in registers beside J.
+    double r, d[4], unused;
+    {
+        double w[4][3], dw[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) phase_weights(ph[k], w[k], dw[k]);
+        if constexpr (DERIV) contract81_sweep<0, 1, kKeep, kThreads>(J, s_box, w, dw, r, d[0], d[1]);
+        else contract81_sweep<-1, -1, kKeep, kThreads>(J, s_box, w, dw, r, unused, unused);
+    }
+    if constexpr (DERIV) {
+#pragma unroll
+        for (int q = 0; q < kKeep; ++q) asm volatile("" : "+v"(J[q]));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(ph[k]));
+        asm volatile("" ::: "memory");
+        double w[4][3], dw[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) phase_weights(ph[k], w[k], dw[k]);
+        contract81_sweep<2, 3, kKeep, kThreads>(J, s_box, w, dw, unused, d[2], d[3]);
+    }
     const double outv = ldexp_neg(r, F) / den;
     if (a.out) a.out[idx] = (float)outv;
-    if (a.dsteps) {
+    if (DERIV && a.dsteps) {
         // d phi / d s = 1/2, and each step enters prod s twice
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -1172,8 +1189,15 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
     } else if (s.kind == 3) {
         hipLaunchKernelGGL((k_gather_t2n4_fp64<BATCH>), grid, block, 0, st, one, table, prefix, B);
     } else if (s.kind == 4) {
-        if (s.tile_h == 4) hipLaunchKernelGGL((k_gather_t2n4_box<BATCH, 4>), grid, block, 0, st, one, table, prefix, B);
-        else hipLaunchKernelGGL((k_gather_t2n4_box<BATCH, 8>), grid, block, 0, st, one, table, prefix, B);
+        // the batched forward never asks for step derivatives
+        const bool deriv = !BATCH && one.dsteps;
+        if (s.tile_h == 4) {
+            if (deriv) hipLaunchKernelGGL((k_gather_t2n4_box<false, 4, true>), grid, block, 0, st, one, table, prefix, B);
+            else hipLaunchKernelGGL((k_gather_t2n4_box<BATCH, 4, false>), grid, block, 0, st, one, table, prefix, B);
+        } else {
+            if (deriv) hipLaunchKernelGGL((k_gather_t2n4_box<false, 8, true>), grid, block, 0, st, one, table, prefix, B);
+            else hipLaunchKernelGGL((k_gather_t2n4_box<BATCH, 8, false>), grid, block, 0, st, one, table, prefix, B);
+        }
     } else if (s.kind == 2) {
         const bool contig = one.off[6] == 1;
         if (!contig) hipLaunchKernelGGL((k_gather_t2n4<false, 2, 16, BATCH>), grid, block, 0, st, one, table, prefix, B);
