@@ -31,9 +31,10 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 INT64_OPS_PER_PIXEL = (729 + 243 + 81 + 27) * 8
 
 
-def measured_traffic():
-    """HBM bytes per launch of the tap kernel from the committed counter runs
-    (profiles/traffic.json), or None when the kernel source has changed since
+def measured_traffic(box_h):
+    """HBM bytes per launch of the tap kernel instance the timed run used (tile
+    height box_h, no step derivatives) from the committed counter runs
+    (profiles/traffic.json), or None when the kernel sources have changed since
     they were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -47,7 +48,8 @@ def measured_traffic():
             h.update(fh.read())
     if h.hexdigest() != rec.get("sha256"):
         return None
-    return rec.get("bytes_per_launch")
+    entry = rec.get("kernels", {}).get("k_gather_t2n4_box<false, %d, false>" % box_h)
+    return None if entry is None else entry.get("bytes_per_launch")
 
 
 def log(*a):
@@ -103,6 +105,7 @@ def main():
         tuning = tuner.tune(cfg, H, W, dev, img=img, steps=steps)
         log("tuned in %.1f s: gather_wx %d line_tl %d box_h %d" % (time.time() - t, tuning["gather_wx"],
                                                                    tuning["line_tl"], tuning["box_h"]))
+    box_h = bsf.get_box_tile()  # the tap kernel's tile for the timed forward
     geo = bsf.plan(cfg, H, W)
     ws = bsf.Workspace(geo.workspace_bytes, dev)
     out = torch.empty((H, W), dtype=torch.float32, device=dev)
@@ -438,6 +441,7 @@ def main():
 
     ops = INT64_OPS_PER_PIXEL * H * W
     achieved = ops / (apply_ms / 1e3) / 1e12
+    traffic = measured_traffic(box_h)
     res = {
         "metric": METRIC,
         "value": mpx,
@@ -456,7 +460,8 @@ def main():
                    "H": H, "W": W, "order": 2, "n_dirs": 4, "max_step": d["max_step"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / ALU_PEAK_TOPS, "traffic": measured_traffic(),
+                     "frac": achieved / ALU_PEAK_TOPS,
+                     "traffic": traffic,
                      "kernel": "per-pixel taps (forward_apply)", "kernel_ms": apply_ms},
         "cpu_baseline": cpu,
         "stages_ms": {"prepare": prep_ms, "apply": apply_ms, "wall_per_step": wall},
@@ -471,7 +476,10 @@ def main():
                 "frac": forward_bytes / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                 "algorithmic_bytes": forward_bytes, "minimum_bytes": minimum_bytes,
                 "minimum_gbs": minimum_bytes / (step_ms / 1e3) / 1e9,
-                "peak_gbs": HBM_PEAK_GBS},
+                "peak_gbs": HBM_PEAK_GBS,
+                # the tap kernel's calibrated counter bytes over its stage time
+                "tap_kernel_measured_bytes": traffic,
+                "tap_kernel_measured_gbs": None if traffic is None else traffic / (apply_ms / 1e3) / 1e9},
         "differentiation": diff,
         "alg3": alg3,
         "tuning": None if tuning is None else {k: tuning[k] for k in ("gather_wx", "line_tl", "box_h")},
