@@ -29,6 +29,9 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # exact separable contraction of the 9^4 taps of one pixel: 729 + 243 + 81 + 27
 # groups of nine values reduced to three operator outputs, 8 int64 adds each
 INT64_OPS_PER_PIXEL = (729 + 243 + 81 + 27) * 8
+FP64_PEAK_TFLOPS = 78.6
+# wave instructions per second: 256 CUs, each one VALU wave instruction per clock
+VALU_ISSUE_PER_S = 256 * 2.4e9
 
 
 def measured_traffic(box_h):
@@ -50,6 +53,23 @@ def measured_traffic(box_h):
         return None
     entry = rec.get("kernels", {}).get("k_gather_t2n4_box<false, %d, false>" % box_h)
     return None if entry is None else entry.get("bytes_per_launch")
+
+
+def alg3_counters():
+    """FP64 flops and VALU instructions per launch of the Alg. 3 kernel from the
+    committed counter run (profiles/alg3_counters.json), or None when its source
+    has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "alg3_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for name in rec.get("sources", []):
+        with open(os.path.join(ROOT, name), "rb") as fh:
+            h.update(fh.read())
+    return rec if h.hexdigest() == rec.get("sha256") else None
 
 
 def log(*a):
@@ -305,7 +325,17 @@ def main():
                          pix=np.array([(y - y0) * (x1 - x0) + (x - x0)]))[0]
             erra = max(erra, abs(float(o64[y, x]) - ref))
         flags_a, _, _ = wsa.status()
+        # VALU-bound: FP64 flops the hardware counted, against the FP64 vector
+        # peak, and the VALU issue rate (one wave instruction per CU per cycle)
+        ca = alg3_counters() if (Ha, Wa) == (4096, 4096) else None
+        roof_a = None
+        if ca is not None:
+            ach = ca["fp64_flops_per_launch"] / (msa / 1e3) / 1e12
+            roof_a = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": ach / FP64_PEAK_TFLOPS,
+                      "valu_issue_frac": ca["valu_instructions_per_launch"] / (msa / 1e3) / VALU_ISSUE_PER_S}
         alg3 = {"workload": da["name"], "ms_per_step": msa, "value": Ha * Wa / (msa / 1e3) / 1e6,
+                "roofline": roof_a,
                 "unit": "Mpixels/s", "dtype": "f64", "steps": args.alg3_steps,
                 "max_abs_err_vs_oracle": erra, "pixels_checked": 16, "device_flags": flags_a,
                 "step_percentiles_50_99_100": [float(v) for v in np.percentile(sa, [50, 99, 100])]}

@@ -25,7 +25,8 @@
  *                      line.  This equals reading the running sum linearly
  *                      between lattice points along u_j, the one-direction
  *                      restriction of the box-spline interpolation of
- *                      eq. interpolation.
+ *                      eq. interpolation.  bsf_filter_alg3 computes the
+ *                      paper's own two-dimensional form of Alg. 3 in FP64.
  *
  * Arithmetic.  The running sums and the signed tap combination are exact
  * two's-complement integers modulo 2^64 (BSF_ARITH_EXACT): a float image is
@@ -160,8 +161,13 @@ bsf_status bsf_preintegrate(const bsf_config *cfg, bsf_dtype dtype, const void *
                             void *G, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Forward filter (the whole hot path: fixed-point load, running sums, per-pixel
- * signed taps with the pixel's own steps, exact combination, normalisation).
+ * Forward filter, the whole hot path: the running sums of the image along every
+ * direction (Section 1.1, first step of BoxFilter; Alg. 3 step 2), then at each
+ * pixel the signed taps of the running sums at the pixel's own steps, combined
+ * and divided by the product of the steps (Section 1.1, second step of
+ * BoxFilter; Alg. 3 step 3; the signs and the weight w of Table 1; the shift
+ * of eq. shifts), with the fixed-point load and the exact combination
+ * described above.
  *   steps:       FP32 [planes][H][W].
  *   out:         FP32 [H][W] (nullable).
  *   out_num:     int64 [H][W] numerators, integer-step mode only (nullable):
@@ -209,7 +215,10 @@ bsf_status bsf_forward_apply(const bsf_config *cfg, bsf_dtype dtype, int64_t H, 
 
 /*
  * Adjoint of the forward filter with continuous steps (differentiation of a
- * loss through the filter).  Given the upstream gradient gout [H][W] of a scalar loss L:
+ * loss through the filter; the paper does not differentiate its filter: this
+ * is the transpose of the linear map of Section 1.1 in the image, and the
+ * derivative of its continuous-step form in the steps).  Given the upstream
+ * gradient gout [H][W] of a scalar loss L:
  *   grad_img   [H][W]          dL/df = K^T gout (nullable), computed as the scatter
  *                              of the pixel's tap patterns weighted in fixed point
  *                              by gout / prod s times the phase products, followed
@@ -228,8 +237,9 @@ bsf_status bsf_filter_backward(const bsf_config *cfg, int64_t H, int64_t W, cons
 
 /*
  * Batched forward over B images of uneven sizes (FP32 images, one shared
- * configuration; the forward of bsf_filter_varying applied to each image, with
- * results identical to B separate calls).  descs is a host array of B entries:
+ * configuration; the forward of bsf_filter_varying, i.e. the two steps of
+ * BoxFilter in Section 1.1, applied to each image, with results identical to B
+ * separate calls; the paper filters one image at a time).  descs is a host array of B entries:
  * img FP32 [H][pitch], steps FP32 [planes][H][W], out FP32 [H][W], all device
  * pointers owned by the caller; H = 0 or W = 0 skips an entry.  Each stage of
  * the path is one launch over the whole batch (a work list of (image, tile)
