@@ -50,6 +50,21 @@ __device__ __forceinline__ bool tile_of_block(const GatherArgs &one, const Gathe
     return true;
 }
 
+// Tile of work item `item` in an image of tiles_x x tiles_y tiles: bands of
+// `band` tile rows, each band taken column by column.  The items one XCD runs
+// at the same time then cover a block about as tall as it is wide (a few tens
+// of tiles each way) instead of a strip one tile row high, and the boxes of
+// the window its tiles read, which are offset from the tile by up to the
+// steps' reach in every direction, stay in its L2 for all the combinations.
+__device__ __forceinline__ void banded_tile(int64_t item, int64_t tiles_x, int64_t tiles_y, int band, int64_t &bx,
+                                            int64_t &by) {
+    const int64_t per_band = (int64_t)band * tiles_x;
+    const int64_t b = item / per_band, in = item - b * per_band;
+    const int64_t h = min((int64_t)band, tiles_y - b * band);  // rows of this band (the last may be short)
+    bx = in / h;
+    by = b * band + in % h;
+}
+
 // As tile_of_block, for a 1-D grid of xcd_grid(tiles) blocks in XCD order.
 template <bool BATCH>
 __device__ __forceinline__ bool tile_of_block_xcd(const GatherArgs &one, const GatherArgs *__restrict__ table,
@@ -62,16 +77,14 @@ __device__ __forceinline__ bool tile_of_block_xcd(const GatherArgs &one, const G
         const int b = find_job(prefix, B, gi);
         a = table[b];
         const int64_t item = gi - prefix[b];
-        const int64_t tiles_x = (a.W + tile_w - 1) / tile_w;
-        bx = item % tiles_x;
-        by = item / tiles_x;
+        const int64_t tiles_x = (a.W + tile_w - 1) / tile_w, tiles_y = (a.H + tile_h - 1) / tile_h;
+        banded_tile(item, tiles_x, tiles_y, 64 / tile_h, bx, by);
     } else {
         a = one;
         const int64_t tiles_x = (a.W + tile_w - 1) / tile_w, tiles_y = (a.H + tile_h - 1) / tile_h;
         const int64_t item = xcd_item(blockIdx.x, tiles_x * tiles_y);
         if (item >= tiles_x * tiles_y) return false;
-        bx = item % tiles_x;
-        by = item / tiles_x;
+        banded_tile(item, tiles_x, tiles_y, 64 / tile_h, bx, by);
     }
     return true;
 }
