@@ -256,3 +256,52 @@ def test_box_tile_setter_validates():
         assert bsf.get_box_tile() == 4
     finally:
         bsf.set_box_tile(h0)
+
+
+TABLE1 = ((2, 1), (1, 2), (1, -2), (2, -1))
+
+
+def test_alg3_sizes_and_limits():
+    """Alg. 3: four directions at order 1, tied, continuous steps; max_step is
+    limited by the LDS rectangle one pixel needs (S <= 21 for the directions of
+    Table 1: (floor(6 S) + 6 + 1)^2 FP64 values within 148 KiB)."""
+    L = bsf.lib()
+    ws = lambda cfg, H=64, W=80: L.bsf_alg3_workspace_bytes(ctypes.byref(cfg.c()), H, W)
+    ok = bsf.Config(dirs=TABLE1, order=1, max_step=21.0)
+    tiles = 4 * 5
+    assert ws(ok) == 256 + 2 * ((tiles * 4 + 255) // 256 * 256)
+    assert ws(bsf.Config(dirs=TABLE1, order=1, max_step=21.8)) > 0
+    assert ws(bsf.Config(dirs=TABLE1, order=1, max_step=22.0)) == 0
+    assert ws(bsf.Config(dirs=TABLE1, order=2, max_step=4.0)) == 0
+    assert ws(bsf.Config(dirs=TABLE1[:3], order=1, max_step=4.0)) == 0
+    assert ws(bsf.Config(dirs=TABLE1, order=1, max_step=4.0, mode=bsf.STEPS_INT)) == 0
+    assert ws(bsf.Config(dirs=TABLE1, order=1, max_step=4.0, tied=False)) == 0   # the documented contract: tied
+    # the directions of Section 1.1 reach less far: larger steps fit
+    assert ws(bsf.Config(dirs=((1, 0), (0, 1), (1, 1), (1, -1)), order=1, max_step=40.0)) > 0
+
+
+def test_alg3_entry_point_validates_before_launch():
+    L = bsf.lib()
+    cfg = bsf.Config(dirs=TABLE1, order=1, max_step=8.0).c()
+    P = ctypes.c_void_p
+    need = L.bsf_alg3_workspace_bytes(ctypes.byref(cfg), 8, 8)
+    # no output at all
+    r = L.bsf_filter_alg3(ctypes.byref(cfg), bsf.F32, P(16), 8, 8, 8, P(16), None, None, P(16), need, None)
+    assert r == bsf.E_INVALID
+    # pitch < W, bad dtype, null workspace
+    r = L.bsf_filter_alg3(ctypes.byref(cfg), bsf.F32, P(16), 8, 8, 4, P(16), P(16), None, P(16), need, None)
+    assert r == bsf.E_INVALID
+    r = L.bsf_filter_alg3(ctypes.byref(cfg), 9, P(16), 8, 8, 8, P(16), P(16), None, P(16), need, None)
+    assert r == bsf.E_INVALID
+    r = L.bsf_filter_alg3(ctypes.byref(cfg), bsf.F32, P(16), 8, 8, 8, P(16), P(16), None, None, need, None)
+    assert r == bsf.E_INVALID
+    # workspace too small
+    r = L.bsf_filter_alg3(ctypes.byref(cfg), bsf.F32, P(16), 8, 8, 8, P(16), P(16), None, P(16), need - 1, None)
+    assert r == bsf.E_WORKSPACE
+    # configurations it does not take
+    bad = bsf.Config(dirs=TABLE1, order=2, max_step=8.0).c()
+    r = L.bsf_filter_alg3(ctypes.byref(bad), bsf.F32, P(16), 8, 8, 8, P(16), P(16), None, P(16), need, None)
+    assert r == bsf.E_UNSUPPORTED
+    # an empty image enqueues nothing
+    r = L.bsf_filter_alg3(ctypes.byref(cfg), bsf.F32, P(16), 0, 8, 8, P(16), P(16), None, P(16), need, None)
+    assert r == bsf.OK
