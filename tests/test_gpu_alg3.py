@@ -160,3 +160,18 @@ def test_alg3_full_size_sampled():
         ref = O.alg3(crop, TABLE1, st, pix=np.array([(y - y0) * (x1 - x0) + (x - x0)]))[0]
         assert abs(o64[y, x] - ref) <= TOL, (x, y, o64[y, x], ref)
     np.testing.assert_array_equal(o32, o64.astype(np.float32))
+
+
+def test_alg3_every_pixel_2048():
+    """Every pixel of the covariance-field workload at 2048 x 2048 (steps from
+    bsf_cov_to_steps for the box spline of Table 1) against the oracle's
+    Alg. 3 on the whole frame."""
+    d = WL.workload_alg3(2048, 2048)
+    H, W = d["img"].shape
+    note("alg3 every pixel", H, W)
+    cfg = bsf.Config(dirs=TABLE1, order=1, max_step=d["max_step"])
+    steps = bsf.cov_to_steps(cfg, to_dev(d["cov"])).cpu().numpy()
+    o32, o64, flags = run(cfg, d["img"], steps)
+    assert flags == 0
+    ref = O.alg3(d["img"], TABLE1, steps)
+    check(o32, o64, ref, 1.0)
