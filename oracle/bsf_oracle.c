@@ -842,7 +842,11 @@ double bsfo_unit_box_spline(const int *dirs, double x, double y)
  * y >= 0, so a point (x, y) depends only on points (x', y') with y' <= y and
  * x' <= x + c (y - y'), c = max ceil(-dx/dy) over directions with dx < 0, and
  * the sums vanish left of x = -c y.  No pass is cut short, so g is the running
- * sum of the zero-extended image, accumulated in long double.
+ * sum of the zero-extended image, accumulated in long double.  Those sums grow
+ * like the fourth power of the region's side (about 1e12 max|f| for a 2048^2
+ * frame), and their rounding with them: large frames are compared block by
+ * block, on crops that hold each block's footprints (the result at a pixel
+ * depends on nothing else).
  *
  * Step 3 takes the 16 taps of Table 1 in the order of dirs (bit k of the tap
  * index moves the tap by -s_k u_k, the sign is (-1)^(number of set bits)), the

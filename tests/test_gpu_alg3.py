@@ -165,7 +165,10 @@ def test_alg3_full_size_sampled():
 def test_alg3_every_pixel_2048():
     """Every pixel of the covariance-field workload at 2048 x 2048 (steps from
     bsf_cov_to_steps for the box spline of Table 1) against the oracle's
-    Alg. 3 on the whole frame."""
+    Alg. 3, block by block: each 128 x 128 block on a crop that holds its
+    pixels' footprints (the filter reads nothing outside them).  Over the
+    whole frame the oracle's own running sums, of order four, would reach
+    about 1e12 max|f| and lose the digits this comparison needs."""
     d = WL.workload_alg3(2048, 2048)
     H, W = d["img"].shape
     note("alg3 every pixel", H, W)
@@ -173,5 +176,19 @@ def test_alg3_every_pixel_2048():
     steps = bsf.cov_to_steps(cfg, to_dev(d["cov"])).cpu().numpy()
     o32, o64, flags = run(cfg, d["img"], steps)
     assert flags == 0
-    ref = O.alg3(d["img"], TABLE1, steps)
-    check(o32, o64, ref, 1.0)
+    np.testing.assert_array_equal(o32, o64.astype(np.float32))
+    S = float(steps.max())
+    mx = int(np.ceil(0.5 * S * sum(abs(u[0]) for u in TABLE1))) + 4
+    my = int(np.ceil(0.5 * S * sum(abs(u[1]) for u in TABLE1))) + 4
+    B = 128
+    worst = 0.0
+    for y0 in range(0, H, B):
+        for x0 in range(0, W, B):
+            cx0, cx1, cy0, cy1 = max(0, x0 - mx), min(W, x0 + B + mx), max(0, y0 - my), min(H, y0 + B + my)
+            crop = np.ascontiguousarray(d["img"][cy0:cy1, cx0:cx1])
+            st = np.ascontiguousarray(steps[:, cy0:cy1, cx0:cx1])
+            ys, xs = np.mgrid[y0:min(H, y0 + B), x0:min(W, x0 + B)]
+            pix = ((ys - cy0) * (cx1 - cx0) + (xs - cx0)).ravel()
+            ref = O.alg3(crop, TABLE1, st, pix=pix).reshape(ys.shape)
+            worst = max(worst, float(np.abs(o64[y0:y0 + B, x0:x0 + B] - ref).max()))
+    assert worst <= TOL, worst
