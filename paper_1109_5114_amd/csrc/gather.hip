@@ -343,8 +343,10 @@ __global__ __launch_bounds__(256) void k_gather_int(GatherArgs one, const Gather
                                                     const int64_t *__restrict__ prefix, int B) {
     GatherArgs a;
     int64_t bx, by, x, y;
-    if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
-    if (!pixel_16x16(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
+    if (!tile_of_block_xcd<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
+    // wavefronts of 16 x 4 pixels: a tap of 16 neighbours in a row reads one
+    // 128-byte line of the window
+    if (!pixel_wx<16>(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
     const int M = MT > 0 ? MT : a.M;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
@@ -1180,7 +1182,7 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
                          int64_t total_tiles, hipStream_t st) {
     const GatherShape s = gather_shape(p, one);
     dim3 grid;
-    if (s.kind == 4) {
+    if (s.kind == 4 || s.kind == 0) {  // tiles in XCD order (tile_of_block_xcd)
         const int64_t tiles = BATCH ? total_tiles
                                     : ((p.W + s.tile_w - 1) / s.tile_w) * ((p.H + s.tile_h - 1) / s.tile_h);
         grid = dim3((unsigned)xcd_grid(tiles));
