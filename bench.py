@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--alg3-size", type=int, default=4096, help="Alg. 3 workload side (0: skip)")
     ap.add_argument("--alg3-steps", type=int, default=5)
+    ap.add_argument("--alg2-size", type=int, default=4096, help="Alg. 2 workload side (0: skip)")
+    ap.add_argument("--alg2-steps", type=int, default=3)
+    ap.add_argument("--alg2-order", type=int, default=1, help="order of Alg. 2's box splines (the paper's is 1)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, one device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -342,6 +345,51 @@ def main():
         log("alg3 %dx%d: %.3f ms, max abs err %.2e" % (Ha, Wa, msa, erra))
         del imga, stepsa, wsa, outa, out64a
 
+    # ---- Alg. 2: both four-direction sets, each pixel filtered by the set its
+    # orientation sector picks, against one set alone (the paper puts the cost
+    # of the second set at 10-15 %)
+    alg2 = None
+    if args.alg2_size > 0:
+        d2 = WL.workload_alg3(args.alg2_size, args.alg2_size)
+        H2, W2 = d2["img"].shape
+        img2 = torch.from_numpy(d2["img"]).to(dev)
+        cov2 = torch.from_numpy(d2["cov"]).to(dev)
+        cfg2 = bsf.Config(order=args.alg2_order, tied=True, mode=bsf.STEPS_REAL, max_step=64.0)
+        ws2 = bsf.Workspace(bsf.lib().bsf_alg2_workspace_bytes(bsf.ctypes.byref(cfg2.c()), H2, W2), dev)
+        bank2 = torch.empty((H2, W2), dtype=torch.uint8, device=dev)
+        out2 = torch.empty((H2, W2), dtype=torch.float32, device=dev)
+        wsc = bsf.Workspace(256, dev)
+        steps1 = torch.empty((4, H2, W2), dtype=torch.float32, device=dev)
+        ws1 = bsf.Workspace(bsf.plan(cfg2, H2, W2).workspace_bytes, dev)
+
+        def two_sets():
+            bsf.filter_alg2(cfg2, img2, cov2, out=out2, bank=bank2, ws=ws2)
+
+        def one_set():
+            bsf.cov_to_steps(cfg2, cov2, steps=steps1, ws=wsc)
+            bsf.forward_prepare(cfg2, img2, steps1, ws1)
+            bsf.forward_apply(cfg2, bsf.F32, steps1, ws1, out2)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t = []
+            for _ in range(args.alg2_steps):
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t.append(e0.elapsed_time(e1))
+            return float(np.median(t))
+        ms_two, ms_one = timed(two_sets), timed(one_set)
+        frac2 = float(bank2.float().mean().item())
+        alg2 = {"workload": "%dx%d covariance field (sigma 2-12 px), order %d" % (H2, W2, args.alg2_order),
+                "ms_two_sets": ms_two, "ms_one_set": ms_one, "cost_ratio": ms_two / ms_one,
+                "pixels_on_second_set": frac2, "steps": args.alg2_steps}
+        log("alg2 %dx%d: two sets %.3f ms, one set %.3f ms (x%.2f), %.0f%% of pixels on the second"
+            % (H2, W2, ms_two, ms_one, ms_two / ms_one, 100 * frac2))
+        del img2, cov2, ws2, bank2, out2, steps1, ws1
+
     # ---- integer steps on a uint8 image: exact int64 numerator and prod s
     integer = None
     if args.int_size > 0:
@@ -512,6 +560,7 @@ def main():
                 "tap_kernel_measured_gbs": None if traffic is None else traffic / (apply_ms / 1e3) / 1e9},
         "differentiation": diff,
         "alg3": alg3,
+        "alg2": alg2,
         "tuning": None if tuning is None else {k: tuning[k] for k in ("gather_wx", "line_tl", "box_h")},
     }
     print(json.dumps(res))

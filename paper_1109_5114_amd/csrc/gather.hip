@@ -408,8 +408,8 @@ __global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs one, con
                                                              const int64_t *__restrict__ prefix, int B) {
     GatherArgs a;
     int64_t bx, by, x, y;
-    if (!tile_of_block<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
-    if (!pixel_16x16(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
+    if (!tile_of_block_xcd<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
+    if (!pixel_wx<16>(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;  // rows of 16: whole lines
     check_pixel_steps(a, y * a.W + x);
     const int M = a.M;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
@@ -1182,7 +1182,7 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
                          int64_t total_tiles, hipStream_t st) {
     const GatherShape s = gather_shape(p, one);
     dim3 grid;
-    if (s.kind == 4 || s.kind == 0) {  // tiles in XCD order (tile_of_block_xcd)
+    if (s.kind == 4 || s.kind == 0 || s.kind == 1) {  // tiles in XCD order (tile_of_block_xcd)
         const int64_t tiles = BATCH ? total_tiles
                                     : ((p.W + s.tile_w - 1) / s.tile_w) * ((p.H + s.tile_h - 1) / s.tile_h);
         grid = dim3((unsigned)xcd_grid(tiles));
