@@ -403,21 +403,27 @@ __global__ __launch_bounds__(256) void k_gather_int(GatherArgs one, const Gather
 // prod_j (e_j ? phi_j : 1 - phi_j).  4^M loads per pixel: the reference path
 // for configurations without a specialised kernel.
 // ----------------------------------------------------------------------------
-template <typename V, bool BATCH>
+// MT > 0 fixes the factor count at compile time (M = 4 is the order-1
+// filter of four directions): the loops unroll and the per-factor arrays live
+// in registers.  MT = 0 takes any M up to BSF_MAX_FACTORS.
+template <typename V, int MT, bool BATCH>
 __global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs one, const GatherArgs *__restrict__ table,
                                                              const int64_t *__restrict__ prefix, int B) {
+    constexpr int MAXF = MT > 0 ? MT : BSF_MAX_FACTORS;
     GatherArgs a;
     int64_t bx, by, x, y;
     if (!tile_of_block_xcd<BATCH>(one, table, prefix, B, kTile, kTile, a, bx, by)) return;
     if (!pixel_wx<16>(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;  // rows of 16: whole lines
     check_pixel_steps(a, y * a.W + x);
-    const int M = a.M;
+    const int M = MT > 0 ? MT : a.M;
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const V *G = static_cast<const V *>(a.G) + (y + a.pad_top) * a.Wp + (x + a.pad_left);
-    int64_t pos[BSF_MAX_FACTORS][4];  // [j][2*e + t]: e = box (0 narrow, 1 wide), t = end (0 top, 1 bottom)
-    double ph[BSF_MAX_FACTORS];
+    int64_t pos[MAXF][4];  // [j][2*e + t]: e = box (0 narrow, 1 wide), t = end (0 top, 1 bottom)
+    double ph[MAXF];
     double den = 1.0;
-    for (int j = 0; j < M; ++j) {
+#pragma unroll
+    for (int j = 0; j < MAXF; ++j) {
+        if (j >= M) break;
         const float s = clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
         const float t = (s - 1.0f) * 0.5f;
         const float R = floorf(t);
@@ -430,28 +436,39 @@ __global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs one, con
         den *= (double)s;
     }
     double tot = 0.0;
-    double dtot[BSF_MAX_FACTORS];
-    for (int j = 0; j < M; ++j) dtot[j] = 0.0;
+    double dtot[MAXF];
+#pragma unroll
+    for (int j = 0; j < MAXF; ++j) dtot[j] = 0.0;
     const bool want_d = a.dsteps != nullptr;
     const int n = 1 << M;
+    // one box choice e at a time (its 2^M loads in flight together)
+#pragma unroll 1
     for (int e = 0; e < n; ++e) {
         double w = 1.0;
-        for (int j = 0; j < M; ++j) w *= (e >> j & 1) ? ph[j] : 1.0 - ph[j];
-        if (w == 0.0 && !want_d) continue;
+#pragma unroll
+        for (int j = 0; j < MAXF; ++j)
+            if (j < M) w *= (e >> j & 1) ? ph[j] : 1.0 - ph[j];
+        if (MT == 0 && w == 0.0 && !want_d) continue;
         V J = V(0);
-        for (int t = 0; t < n; ++t) {
+#pragma unroll
+        for (int t = 0; t < (MT > 0 ? (1 << MT) : n); ++t) {
             int64_t o = 0;
-            for (int j = 0; j < M; ++j) o += pos[j][2 * (e >> j & 1) + (t >> j & 1)];
+#pragma unroll
+            for (int j = 0; j < MAXF; ++j)
+                if (j < M) o += pos[j][2 * (e >> j & 1) + (t >> j & 1)];
             if (__builtin_popcount(t) & 1) J -= G[o];
             else J += G[o];
         }
         tot += w * (double)J;
         if (want_d) {
             // d w / d phi_j: the product over the other factors, signed by the box choice
-            for (int j = 0; j < M; ++j) {
+#pragma unroll
+            for (int j = 0; j < MAXF; ++j) {
+                if (j >= M) break;
                 double dw = (e >> j & 1) ? 1.0 : -1.0;
-                for (int l = 0; l < M; ++l)
-                    if (l != j) dw *= (e >> l & 1) ? ph[l] : 1.0 - ph[l];
+#pragma unroll
+                for (int l = 0; l < MAXF; ++l)
+                    if (l != j && l < M) dw *= (e >> l & 1) ? ph[l] : 1.0 - ph[l];
                 dtot[j] += dw * (double)J;
             }
         }
@@ -465,7 +482,9 @@ __global__ __launch_bounds__(256) void k_gather_real_generic(GatherArgs one, con
         const int planes = a.tied ? a.n_dirs : M;
         for (int q = 0; q < planes; ++q) {
             double d = 0.0;
-            for (int j = 0; j < M; ++j) {
+#pragma unroll
+            for (int j = 0; j < MAXF; ++j) {
+                if (j >= M) break;
                 if (a.plane[j] != q) continue;
                 const double s = (double)clamp_step(a.steps[a.plane[j] * HW + idx], a.max_step);
                 d += 0.5 * ldexp_neg(dtot[j], F) / den - outv / s;
@@ -1221,8 +1240,13 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
         else if (s.tile_w == 64) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 64, BATCH>), grid, block, 0, st, one, table, prefix, B);
         else hipLaunchKernelGGL((k_gather_t2n4<true, 2, 16, BATCH>), grid, block, 0, st, one, table, prefix, B);
     } else {
-        if (fp64) hipLaunchKernelGGL((k_gather_real_generic<double, BATCH>), grid, block, 0, st, one, table, prefix, B);
-        else hipLaunchKernelGGL((k_gather_real_generic<int64_t, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        if (p.M == 4) {
+            if (fp64) hipLaunchKernelGGL((k_gather_real_generic<double, 4, BATCH>), grid, block, 0, st, one, table, prefix, B);
+            else hipLaunchKernelGGL((k_gather_real_generic<int64_t, 4, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        } else {
+            if (fp64) hipLaunchKernelGGL((k_gather_real_generic<double, 0, BATCH>), grid, block, 0, st, one, table, prefix, B);
+            else hipLaunchKernelGGL((k_gather_real_generic<int64_t, 0, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        }
     }
     BSF_HIP_CHECK(hipGetLastError());
     return BSF_OK;
