@@ -614,7 +614,7 @@ __device__ __forceinline__ double contract_fp(const int64_t acc[27], const doubl
 // the current operator a0 are live:
 //   aa: -2 M1, + T0, + B2;   bb: -2 M1, + T2, + B0;   ab: -(M0 + M2), + T1, + B1
 // (M1 is visited twice, 10 steps in all).
-template <bool CONTIG>
+template <bool CONTIG, bool DERIV = true>
 __device__ __forceinline__ void t2n4_pixel(const GatherArgs &a, int64_t x, int64_t y) {
     const int64_t HW = a.H * a.W, idx = y * a.W + x;
     const char *Gb = static_cast<const char *>(a.G);
@@ -666,7 +666,7 @@ __device__ __forceinline__ void t2n4_pixel(const GatherArgs &a, int64_t x, int64
             const int a0 = (i == 2) ? 0 : (i == 5) ? 2 : 1;
             const double r = contract_fp(acc, w[1], w[2], w[3]);
             tot += w[0][a0] * r;
-            if (a.dsteps) {
+            if (DERIV && a.dsteps) {
                 dtot[0] += dw[0][a0] * r;
                 dtot[1] += w[0][a0] * contract_fp(acc, dw[1], w[2], w[3]);
                 dtot[2] += w[0][a0] * contract_fp(acc, w[1], dw[2], w[3]);
@@ -677,7 +677,7 @@ __device__ __forceinline__ void t2n4_pixel(const GatherArgs &a, int64_t x, int64
     const int F = a.status[ST_F_USED];
     const double outv = ldexp_neg(tot, F) / den;
     if (a.out) a.out[idx] = (float)outv;
-    if (a.dsteps) {
+    if (DERIV && a.dsteps) {
         // d phi / d s = 1/2, and the step of direction k enters prod s twice
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -687,7 +687,7 @@ __device__ __forceinline__ void t2n4_pixel(const GatherArgs &a, int64_t x, int64
 
 // WAVES bounds the registers so that that many wavefronts fit on a SIMD; WX
 // is the wavefront's pixel width.
-template <bool CONTIG, int WAVES, int WX, bool BATCH>
+template <bool CONTIG, int WAVES, int WX, bool BATCH, bool DERIV = true>
 __global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, const GatherArgs *__restrict__ table,
                                                             const int64_t *__restrict__ prefix, int B) {
     GatherArgs a;
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(256, WAVES) void k_gather_t2n4(GatherArgs one, cons
     if (!tile_of_block<BATCH>(one, table, prefix, B, WX, 256 / WX, a, bx, by)) return;
     if (!pixel_wx<WX>(a, bx, by, x, y) || !selected(a, y * a.W + x)) return;
     check_pixel_steps(a, y * a.W + x);
-    t2n4_pixel<CONTIG>(a, x, y);
+    t2n4_pixel<CONTIG, DERIV>(a, x, y);
 }
 
 // ----------------------------------------------------------------------------
@@ -1234,7 +1234,10 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
         }
     } else if (s.kind == 2) {
         const bool contig = one.off[6] == 1;
-        if (!contig) hipLaunchKernelGGL((k_gather_t2n4<false, 2, 16, BATCH>), grid, block, 0, st, one, table, prefix, B);
+        if (!contig) {
+            if (one.dsteps) hipLaunchKernelGGL((k_gather_t2n4<false, 2, 16, BATCH>), grid, block, 0, st, one, table, prefix, B);
+            else hipLaunchKernelGGL((k_gather_t2n4<false, 2, 16, BATCH, false>), grid, block, 0, st, one, table, prefix, B);
+        }
         else if (s.tile_w == 8) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 8, BATCH>), grid, block, 0, st, one, table, prefix, B);
         else if (s.tile_w == 32) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 32, BATCH>), grid, block, 0, st, one, table, prefix, B);
         else if (s.tile_w == 64) hipLaunchKernelGGL((k_gather_t2n4<true, 2, 64, BATCH>), grid, block, 0, st, one, table, prefix, B);
