@@ -354,7 +354,12 @@ def main():
         H2, W2 = d2["img"].shape
         img2 = torch.from_numpy(d2["img"]).to(dev)
         cov2 = torch.from_numpy(d2["cov"]).to(dev)
-        cfg2 = bsf.Config(order=args.alg2_order, tied=True, mode=bsf.STEPS_REAL, max_step=64.0)
+        # max_step from the data: the largest step either set needs for this field
+        smax = 1.0
+        for dirs in (((1, 0), (0, 1), (1, 1), (1, -1)), WL.DIRS_TABLE1):
+            probe = bsf.Config(dirs=dirs, order=args.alg2_order, tied=True, mode=bsf.STEPS_REAL, max_step=1e5)
+            smax = max(smax, float(bsf.cov_to_steps(probe, cov2).max().item()))
+        cfg2 = bsf.Config(order=args.alg2_order, tied=True, mode=bsf.STEPS_REAL, max_step=float(np.ceil(smax)))
         ws2 = bsf.Workspace(bsf.lib().bsf_alg2_workspace_bytes(bsf.ctypes.byref(cfg2.c()), H2, W2), dev)
         bank2 = torch.empty((H2, W2), dtype=torch.uint8, device=dev)
         out2 = torch.empty((H2, W2), dtype=torch.float32, device=dev)
@@ -383,7 +388,8 @@ def main():
             return float(np.median(t))
         ms_two, ms_one = timed(two_sets), timed(one_set)
         frac2 = float(bank2.float().mean().item())
-        alg2 = {"workload": "%dx%d covariance field (sigma 2-12 px), order %d" % (H2, W2, args.alg2_order),
+        alg2 = {"workload": "%dx%d covariance field (sigma 2-12 px), order %d, max_step %g"
+                            % (H2, W2, args.alg2_order, cfg2.max_step),
                 "ms_two_sets": ms_two, "ms_one_set": ms_one, "cost_ratio": ms_two / ms_one,
                 "pixels_on_second_set": frac2, "steps": args.alg2_steps}
         log("alg2 %dx%d: two sets %.3f ms, one set %.3f ms (x%.2f), %.0f%% of pixels on the second"
