@@ -620,7 +620,7 @@ bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *sta
     const int64_t n = p.Hp * p.Wp;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)fill_blocks(n)), dim3(256), 0, st, a.Ghat, n);
     BSF_HIP_CHECK(hipGetLastError());
-    if (p.n_dirs == 4 && p.order == 2 && p.tied && a.canon)
+    if (p.n_dirs == 4 && p.order == 2 && p.tied && a.canon == 1)
         hipLaunchKernelGGL(k_adj_scatter_t2n4_box, dim3((unsigned)xcd_grid((int64_t)grid.x * grid.y)), dim3(256), 0,
                            st, a);
     else if (p.n_dirs == 4 && p.order == 2 && p.tied)

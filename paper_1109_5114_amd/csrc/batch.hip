@@ -206,6 +206,7 @@ void build_tables(const bsf_config *cfg, const bsf_image_desc *descs, const Batc
             put<int64_t>(h, bp.t_prefix_groups[k], b + 1, tb.groups[k]);
         }
         GatherArgs a = gather_args(p, G, d.steps, d.out, nullptr, nullptr, nullptr, status);
+        if (a.canon == 2) a.canon = 0;  // no batched cluster-box kernel in the frame of Table 1
         put<GatherArgs>(h, bp.t_gather, b, a);
         if (live) {
             tb.tiles += gather_tiles(p, a);

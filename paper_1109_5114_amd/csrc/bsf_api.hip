@@ -159,15 +159,19 @@ GatherArgs gather_args(const Plan &p, const void *G, const float *steps, float *
             }
     }
     if (p.n_dirs == 4) {
-        static const int kCanon[4][2] = {{1, 0}, {0, 1}, {1, 1}, {1, -1}};
-        int found = 0;
-        for (int c = 0; c < 4; ++c)
-            for (int k = 0; k < 4; ++k)
-                if (p.dx[k] == kCanon[c][0] && p.dy[k] == kCanon[c][1]) {
-                    a.canon_plane[c] = k;
-                    ++found;
-                }
-        a.canon = found == 4 ? 1 : 0;
+        // the two frames of the cluster-box kernels: Section 1.1's directions
+        // and those of Table 1
+        static const int kFrame[2][4][2] = {{{1, 0}, {0, 1}, {1, 1}, {1, -1}}, {{2, 1}, {1, 2}, {1, -2}, {2, -1}}};
+        for (int f = 0; f < 2 && !a.canon; ++f) {
+            int found = 0;
+            for (int c = 0; c < 4; ++c)
+                for (int k = 0; k < 4; ++k)
+                    if (p.dx[k] == kFrame[f][c][0] && p.dy[k] == kFrame[f][c][1]) {
+                        a.canon_plane[c] = k;
+                        ++found;
+                    }
+            if (found == 4) a.canon = f + 1;
+        }
     }
     for (int kk = 0; kk < p.n_dirs; ++kk) {
         const int k = perm[kk];

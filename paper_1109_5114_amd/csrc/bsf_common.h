@@ -134,8 +134,9 @@ struct GatherArgs {
     int32_t off[BSF_MAX_FACTORS];    // window offset (elements) of one lattice step along factor j
     int32_t plane[BSF_MAX_FACTORS];  // step plane of factor j
     // Four directions that are exactly (1,0), (0,1), (1,1), (1,-1) in some
-    // order: canon = 1 and canon_plane[k] is the step plane of the k-th of
-    // those (the cluster-box kernels address taps in that fixed frame).
+    // order: canon = 1; exactly (2,1), (1,2), (1,-2), (2,-1): canon = 2; then
+    // canon_plane[k] is the step plane of the k-th of those (the cluster-box
+    // kernels address taps in that fixed frame).  Otherwise canon = 0.
     int32_t canon;
     int32_t canon_plane[4];
     // nullable: only pixels whose sel entry equals sel_id are written (the
@@ -144,6 +145,9 @@ struct GatherArgs {
     int32_t sel_id;
 };
 bsf_status run_gather(const Plan &p, const GatherArgs &a, hipStream_t st);
+// The tied order-2 cluster-box gather of one image in the frame of Table 1's
+// directions (canon = 2), launched on the given grid (gather_f1.hip).
+bsf_status launch_gather_f1(const GatherArgs &a, dim3 grid, dim3 block, hipStream_t st);
 // Arguments of the gather for one image (bsf_api.hip).
 GatherArgs gather_args(const Plan &p, const void *G, const float *steps, float *out, int64_t *num, int64_t *den,
                        float *dsteps, const int32_t *status);

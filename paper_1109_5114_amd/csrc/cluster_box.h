@@ -1,18 +1,21 @@
-// Cluster boxes of the tied order-2 filter along the four directions
-// u_0 = (1,0), u_1 = (0,1), u_2 = (1,1), u_3 = (1,-1) (Section 1.1 with the
-// box factors of Table 1 used twice per direction).
+// Cluster boxes of the tied order-2 filter along four directions u_0..u_3
+// (Section 1.1 with the box factors of Table 1 used twice per direction), in
+// one of two fixed frames: D = 0 is Section 1.1's set (1,0), (0,1), (1,1),
+// (1,-1); D = 1 is the set of Table 1, (2,1), (1,2), (1,-2), (2,-1), that
+// Alg. 2 switches to in the sectors Section 1.1's set covers badly.
 //
 // Along u_k the nine taps of a pixel (Alg. 3 step 3, squared difference
 // operator) lie in three clusters of three consecutive lattice points,
 //     T = 2R + {0,1,2},   M = -2 + {0,1,2},   B = -2R - 4 + {0,1,2},
 // with R = floor((s-1)/2) of the pixel's step.  Picking one cluster per
 // direction (a combination; 81 in all) leaves 3^4 taps that sit at
-// anchor + (q0 + q2 + q3, q1 + q2 - q3), q in {0,1,2}^4: a 7 x 7 patch with
-// 37 distinct points, where anchor = x + sum_k base_k u_k.  Over a tile of
-// pixels the anchors move with the pixel and with 2 (R - R') along u_k, so a
-// combination of a 16 x 16 tile reaches one small box of the running-sum
-// window.  The gather stages that box in LDS and reads it at static offsets;
-// the adjoint accumulates into it and adds it to the window once.
+// anchor + sum_k q_k u_k, q in {0,1,2}^4, where anchor = x + sum_k base_k u_k:
+// in frame 0 a 7 x 7 patch with 37 distinct points, in frame 1 a 13 x 13 patch
+// with 73.  Over a tile of pixels the anchors move with the pixel and with
+// 2 (R - R') along u_k, so a combination of a tile reaches one small box of
+// the running-sum window.  The gather stages that box in LDS and reads it at
+// static offsets; the adjoint accumulates into it and adds it to the window
+// once.
 //
 // The tensor of the 81 exact integer values J[o0][o1][o2][o3] (o = aa, ab,
 // bb per direction; the order-2 operators
@@ -67,13 +70,55 @@ __host__ __device__ constexpr int out_o(int c, int r, int j) {
 __host__ __device__ constexpr int doubled(int c, int r) { return (c == 1 && r == 0) ? 1 : 0; }
 __host__ __device__ constexpr int jidx(int o0, int o1, int o2, int o3) { return ((o0 * 3 + o1) * 3 + o2) * 3 + o3; }
 
-// LDS element offset of sub-tap q from the pixel's base (the patch row Y = -2).
+// The two frames: u_k = (ux[k], uy[k]).  A pixel's patch spans columns
+// X = 0 .. PX - 1 and rows Y = Y0 .. Y0 + PY - 1 around its anchor.
+template <int D>
+struct Frame;
+template <>
+struct Frame<0> {
+    static constexpr int ux[4] = {1, 0, 1, 1};
+    static constexpr int uy[4] = {0, 1, 1, -1};
+};
+template <>
+struct Frame<1> {
+    static constexpr int ux[4] = {2, 1, 1, 2};
+    static constexpr int uy[4] = {1, 2, -2, -1};
+};
+template <int D>
+__host__ __device__ constexpr int patch_w() {
+    return 1 + 2 * (Frame<D>::ux[0] + Frame<D>::ux[1] + Frame<D>::ux[2] + Frame<D>::ux[3]);
+}
+template <int D>
+__host__ __device__ constexpr int patch_h() {
+    int h = 1;
+    for (int k = 0; k < 4; ++k) h += 2 * (Frame<D>::uy[k] < 0 ? -Frame<D>::uy[k] : Frame<D>::uy[k]);
+    return h;
+}
+template <int D>
+__host__ __device__ constexpr int patch_y0() {
+    int y = 0;
+    for (int k = 0; k < 4; ++k) y += Frame<D>::uy[k] < 0 ? 2 * Frame<D>::uy[k] : 0;
+    return y;
+}
+// Offset of sub-tap q from the anchor, and its patch row Y - Y0.
+template <int D>
+__host__ __device__ constexpr int sub_dx(int q0, int q1, int q2, int q3) {
+    return q0 * Frame<D>::ux[0] + q1 * Frame<D>::ux[1] + q2 * Frame<D>::ux[2] + q3 * Frame<D>::ux[3];
+}
+template <int D>
+__host__ __device__ constexpr int sub_row(int q0, int q1, int q2, int q3) {
+    return q0 * Frame<D>::uy[0] + q1 * Frame<D>::uy[1] + q2 * Frame<D>::uy[2] + q3 * Frame<D>::uy[3] - patch_y0<D>();
+}
+
+// LDS element offset of sub-tap q from the pixel's base (its patch row Y0).
+template <int D = 0>
 __host__ __device__ constexpr int sub_elem(int q0, int q1, int q2, int q3) {
-    return (q0 + q2 + q3) + kPitch * (q1 + q2 - q3 + 2);
+    return sub_dx<D>(q0, q1, q2, q3) + kPitch * sub_row<D>(q0, q1, q2, q3);
 }
 
 // The sub-taps q (index q0 + 3 q1 + 9 q2 + 27 q3) at each of the 7 x 7 patch
-// points P = X + 7 (Y + 2); 37 points are hit, by at most five sub-taps.
+// points P = X + 7 (Y + 2) of frame 0; 37 points are hit, by at most five
+// sub-taps.
 struct PatchTable {
     int count[49];
     int q[49][5];
@@ -102,9 +147,10 @@ struct Box {
     int ox, oy, bw, bh;
 };
 
-template <int C>
+template <int C, int D = 0>
 __host__ __device__ __forceinline__ Box box_of(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4], const int Rhi[4],
                                       int pad_left) {
+    using U = Frame<D>;
     int bmin[4], bmax[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -112,19 +158,39 @@ __host__ __device__ __forceinline__ Box box_of(int x_lo, int x_hi, int y_lo, int
         bmin[k] = c == 0 ? 2 * Rlo[k] : c == 1 ? -2 : -2 * Rhi[k] - 4;
         bmax[k] = c == 0 ? 2 * Rhi[k] : c == 1 ? -2 : -2 * Rlo[k] - 4;
     }
-    const int ax_min = x_lo + bmin[0] + bmin[2] + bmin[3], ax_max = x_hi + bmax[0] + bmax[2] + bmax[3];
-    const int ay_min = y_lo + bmin[1] + bmin[2] - bmax[3], ay_max = y_hi + bmax[1] + bmax[2] - bmin[3];
+    int ax_min, ax_max, ay_min, ay_max;
+    if constexpr (D == 0) {
+        ax_min = x_lo + bmin[0] + bmin[2] + bmin[3];
+        ax_max = x_hi + bmax[0] + bmax[2] + bmax[3];
+        ay_min = y_lo + bmin[1] + bmin[2] - bmax[3];
+        ay_max = y_hi + bmax[1] + bmax[2] - bmin[3];
+    } else {
+        ax_min = x_lo, ax_max = x_hi, ay_min = y_lo, ay_max = y_hi;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            ax_min += bmin[k] * U::ux[k];  // ux >= 0 in both frames
+            ax_max += bmax[k] * U::ux[k];
+            ay_min += (U::uy[k] >= 0 ? bmin[k] : bmax[k]) * U::uy[k];
+            ay_max += (U::uy[k] >= 0 ? bmax[k] : bmin[k]) * U::uy[k];
+        }
+    }
     const int odd = (ax_min + pad_left) & 1;
-    return Box{ax_min - odd, ay_min - 2, ax_max - ax_min + 7 + odd, ay_max - ay_min + 7};
+    return Box{ax_min - odd, ay_min + patch_y0<D>(), ax_max - ax_min + patch_w<D>() + odd,
+               ay_max - ay_min + patch_h<D>()};
 }
 
-// LDS element of the pixel's patch row Y = -2, column X = 0.
-template <int C>
+// LDS element of the pixel's patch row Y0, column X = 0.
+template <int C, int D = 0>
 __host__ __device__ __forceinline__ int pixel_base(int x, int y, const int R[4], const Box &b) {
-    const int b0 = base_of(cl(C, 0), R[0]), b1 = base_of(cl(C, 1), R[1]);
-    const int b2 = base_of(cl(C, 2), R[2]), b3 = base_of(cl(C, 3), R[3]);
-    const int ax = x + b0 + b2 + b3, ay = y + b1 + b2 - b3;
-    return (ay - 2 - b.oy) * kPitch + (ax - b.ox);
+    using U = Frame<D>;
+    int ax = x, ay = y;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int bk = base_of(cl(C, k), R[k]);
+        ax += bk * U::ux[k];
+        ay += bk * U::uy[k];
+    }
+    return (ay + patch_y0<D>() - b.oy) * kPitch + (ax - b.ox);
 }
 
 // (These index functions are also compiled for the host, where a test walks
@@ -142,27 +208,28 @@ __host__ __device__ __forceinline__ uint32_t pack_state(int tx, int ty, const in
 }
 
 // pixel_base from the packed state: 64 ty + tx + sum_k coef_k b_k with
-// coef = (1, 64, 65, -63) the LDS offsets of u = (1,0), (0,1), (1,1), (1,-1)
-// and b_k = 2 R_k (T), -2 (M), -2 R_k - 4 (B); the tile-uniform part is
-// formed once per combination.
-template <int C>
+// coef_k = ux_k + 64 uy_k the LDS offset of u_k ((1, 64, 65, -63) in frame 0,
+// (66, 129, -127, -62) in frame 1) and b_k = 2 R_k (T), -2 (M), -2 R_k - 4 (B);
+// the tile-uniform part is formed once per combination.
+template <int C, int D = 0>
 __host__ __device__ __forceinline__ int packed_base(uint32_t st, int x_lo, int y_lo, const int Rlo[4], const Box &b) {
     static_assert(kPitch == 64, "coefficients assume a 64-element pitch");
-    constexpr int coef[4] = {1, 64, 65, -63};
+    using U = Frame<D>;
     int v = (int)(st & 1023u);
-    int sc = kPitch * (y_lo - 2 - b.oy) + (x_lo - b.ox);
+    int sc = kPitch * (y_lo + patch_y0<D>() - b.oy) + (x_lo - b.ox);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int c = cl(C, k);
+        const int coef = U::ux[k] + kPitch * U::uy[k];
         const int dR = (int)((st >> (10 + 5 * k)) & 31u);
         if (c == 0) {
-            v += 2 * coef[k] * dR;
-            sc += 2 * coef[k] * Rlo[k];
+            v += 2 * coef * dR;
+            sc += 2 * coef * Rlo[k];
         } else if (c == 2) {
-            v -= 2 * coef[k] * dR;
-            sc += coef[k] * (-2 * Rlo[k] - 4);
+            v -= 2 * coef * dR;
+            sc += coef * (-2 * Rlo[k] - 4);
         } else {
-            sc += -2 * coef[k];
+            sc += -2 * coef;
         }
     }
     return v + sc;
@@ -170,11 +237,23 @@ __host__ __device__ __forceinline__ int packed_base(uint32_t st, int x_lo, int y
 
 // Largest box over the combinations (all clusters T or B, one column of
 // alignment) fits an LDS box of the given number of rows.
+template <int D = 0>
 __host__ __device__ __forceinline__ bool boxes_fit(int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4],
                                           const int Rhi[4], int rows = kRows) {
+    using U = Frame<D>;
     const int d0 = Rhi[0] - Rlo[0], d1 = Rhi[1] - Rlo[1], d2 = Rhi[2] - Rlo[2], d3 = Rhi[3] - Rlo[3];
-    const int w = (x_hi - x_lo) + 8 + 2 * (d0 + d2 + d3);
-    const int h = (y_hi - y_lo) + 7 + 2 * (d1 + d2 + d3);
+    if constexpr (D == 0) {
+        const int w = (x_hi - x_lo) + 8 + 2 * (d0 + d2 + d3);
+        const int h = (y_hi - y_lo) + 7 + 2 * (d1 + d2 + d3);
+        return w <= kPitch && h <= rows;
+    }
+    const int d[4] = {d0, d1, d2, d3};
+    int w = (x_hi - x_lo) + patch_w<D>() + 1, h = (y_hi - y_lo) + patch_h<D>();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        w += 2 * d[k] * U::ux[k];
+        h += 2 * d[k] * (U::uy[k] < 0 ? -U::uy[k] : U::uy[k]);
+    }
     return w <= kPitch && h <= rows;
 }
 

@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "bsf_common.h"
 #include "cluster_box.h"
@@ -831,6 +832,105 @@ __device__ __forceinline__ void box_fwd_combo(const uint64_t *__restrict__ p, co
     box_fwd_pass<C, 2>(val, J);
 }
 
+// Frame 1 (the directions of Table 1, (2,1), (1,2), (1,-2), (2,-1)): the
+// 81 sub-taps of a combination fall on 73 distinct points of a 13 x 13 patch,
+// one or two per point, so each sub-tap is added into its targets on its own
+// (a T tap q feeds o = q, a B tap o = 2 - q, M1 both aa and bb doubled, M0 and
+// M2 ab).  The patch is read in four batches of rows, each from its own
+// opaque LDS base, and a batch's sub-taps are added before the next batch is
+// loaded, so that at most 23 values wait in registers beside J.
+struct F1Points {
+    bool hit[13 * 13];  // point X + 13 Y of the patch is some sub-tap's
+};
+__host__ __device__ constexpr F1Points make_f1_points() {
+    F1Points t{};
+    for (int q = 0; q < 81; ++q) {
+        const int q0 = q % 3, q1 = (q / 3) % 3, q2 = (q / 9) % 3, q3 = q / 27;
+        t.hit[cbox::sub_dx<1>(q0, q1, q2, q3) + 13 * cbox::sub_row<1>(q0, q1, q2, q3)] = true;
+    }
+    return t;
+}
+constexpr F1Points kF1Points = make_f1_points();
+
+// Target j of sub-tap q in combination C (its J index, or -1 past the last):
+// a T tap q feeds o = q, a B tap o = 2 - q, M0 and M2 ab, and M1 both aa and
+// bb (bit b of j picks between them for the b-th such direction); f1_shift is
+// the number of those doublings.  Everything here is a template constant, so
+// that every J index is known at compile time.
+__host__ __device__ constexpr int f1_target(int C, int q, int j) {
+    int idx = 0, bit = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int c = cbox::cl(C, k), qk = k == 0 ? q % 3 : k == 1 ? (q / 3) % 3 : k == 2 ? (q / 9) % 3 : q / 27;
+        int o;
+        if (c == 1 && qk == 1) {
+            o = ((j >> bit) & 1) ? 2 : 0;
+            ++bit;
+        } else {
+            o = c == 0 ? qk : c == 2 ? 2 - qk : 1;
+        }
+        idx = idx * 3 + o;
+    }
+    return j < (1 << bit) ? idx : -1;
+}
+__host__ __device__ constexpr int f1_shift(int C, int q) {
+    int n = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int qk = k == 0 ? q % 3 : k == 1 ? (q / 3) % 3 : k == 2 ? (q / 9) % 3 : q / 27;
+        n += cbox::cl(C, k) == 1 && qk == 1;
+    }
+    return n;
+}
+
+template <int T, int SH>
+__device__ __forceinline__ void f1_add(uint64_t J[81], uint64_t v) {
+    if constexpr (T >= 0) shl_add(J[T], v, SH);
+}
+
+template <int C, int Y_BEGIN, int Y_END, int Q, int... Js>
+__device__ __forceinline__ void f1_subtap(const uint64_t *val, uint64_t J[81], std::integer_sequence<int, Js...>) {
+    constexpr int q0 = Q % 3, q1 = (Q / 3) % 3, q2 = (Q / 9) % 3, q3 = Q / 27;
+    constexpr int Y = cbox::sub_row<1>(q0, q1, q2, q3);
+    if constexpr (Y >= Y_BEGIN && Y < Y_END) {
+        const uint64_t v = val[(Y - Y_BEGIN) * cbox::patch_w<1>() + cbox::sub_dx<1>(q0, q1, q2, q3)];
+        (f1_add<f1_target(C, Q, Js), f1_shift(C, Q)>(J, v), ...);
+    }
+}
+
+template <int C, int Y_BEGIN, int Y_END, int... Qs>
+__device__ __forceinline__ void f1_subtaps(const uint64_t *val, uint64_t J[81], std::integer_sequence<int, Qs...>) {
+    (f1_subtap<C, Y_BEGIN, Y_END, Qs>(val, J, std::make_integer_sequence<int, 16>{}), ...);
+}
+
+template <int C, int Y_BEGIN, int Y_END>
+__device__ __forceinline__ void box_fwd_rows_f1(const uint64_t *__restrict__ p, uint64_t J[81]) {
+    using namespace cbox;
+    constexpr int PW = patch_w<1>();
+    uint64_t val[(Y_END - Y_BEGIN) * PW];
+#pragma unroll
+    for (int Y = Y_BEGIN; Y < Y_END; ++Y)
+#pragma unroll
+        for (int X = 0; X < PW; ++X)
+            if (kF1Points.hit[X + PW * Y]) val[(Y - Y_BEGIN) * PW + X] = p[X + kPitch * (Y - Y_BEGIN)];
+    f1_subtaps<C, Y_BEGIN, Y_END>(val, J, std::make_integer_sequence<int, 81>{});
+}
+
+template <int C, int Y_BEGIN, int Y_END>
+__device__ __forceinline__ void box_fwd_batch_f1(int base, const uint64_t *__restrict__ s_box, uint64_t J[81]) {
+    int b = base + cbox::kPitch * Y_BEGIN;
+    asm("" : "+v"(b));
+    box_fwd_rows_f1<C, Y_BEGIN, Y_END>(s_box + b, J);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int C>
+__device__ __forceinline__ void box_fwd_combo_f1(int base, const uint64_t *__restrict__ s_box, uint64_t J[81]) {
+    static_assert(cbox::patch_h<1>() == 13, "four row batches cover the patch");
+    box_fwd_batch_f1<C, 0, 5>(base, s_box, J);
+    box_fwd_batch_f1<C, 5, 7>(base, s_box, J);
+    box_fwd_batch_f1<C, 7, 9>(base, s_box, J);
+    box_fwd_batch_f1<C, 9, 13>(base, s_box, J);
+}
+
 // Start copying box b of the window into the LDS buffer dst (rows of kPitch
 // elements) with LDS-direct loads: one instruction moves two box rows as 64
 // aligned pairs of elements (lane l: row l / 32, elements 2 (l % 32) and the
@@ -879,14 +979,14 @@ struct BoxTile {
 // Combination I reads buffer I % 2 while combination I + 1 is copied into the
 // other one; one barrier per combination publishes the next box and frees the
 // current one.
-template <int I, class S>
+template <int I, class S, int D>
 __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__restrict__ s_box, bool active,
                                             const BoxTile &t, uint64_t J[81]) {
     constexpr int C = cbox::order_at(I);
-    const cbox::Box b = cbox::box_of<C>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left);
+    const cbox::Box b = cbox::box_of<C, D>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left);
     if constexpr (I + 1 < cbox::kCombos) {
         constexpr int Cn = cbox::order_at(I + 1);
-        const cbox::Box bn = cbox::box_of<Cn>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left);
+        const cbox::Box bn = cbox::box_of<Cn, D>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left);
         box_stage_async<S::Waves>(a, s_box + ((I + 1) & 1) * S::Elems, bn, t.wave);
     }
     if constexpr (I == cbox::kEven) {
@@ -898,14 +998,18 @@ __device__ __forceinline__ void box_fwd_all(const GatherArgs &a, uint64_t *__res
         // afresh from the lane number: neither the state, its decoded fields
         // nor its address stay live across combinations
         const uint32_t st = t.state[64 * t.wave + fresh_lane_id()];
-        int base = (I & 1) * S::Elems + cbox::packed_base<C>(st, t.x_lo, t.y_lo, t.Rlo, b);
-        int base_hi = base + 4 * cbox::kPitch;
-        asm("" : "+v"(base), "+v"(base_hi));
-        box_fwd_combo<C>(s_box + base, s_box + base_hi, J);
+        const int base = (I & 1) * S::Elems + cbox::packed_base<C, D>(st, t.x_lo, t.y_lo, t.Rlo, b);
+        if constexpr (D == 0) {
+            int lo = base, hi = base + 4 * cbox::kPitch;
+            asm("" : "+v"(lo), "+v"(hi));
+            box_fwd_combo<C>(s_box + lo, s_box + hi, J);
+        } else {
+            box_fwd_combo_f1<C>(base, s_box, J);
+        }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if constexpr (I + 1 < cbox::kCombos) box_fwd_all<I + 1, S>(a, s_box, active, t, J);
+    if constexpr (I + 1 < cbox::kCombos) box_fwd_all<I + 1, S, D>(a, s_box, active, t, J);
 }
 
 // The 81-term contraction of J with the phase weights: the value (weights w
@@ -1005,7 +1109,9 @@ __device__ __forceinline__ void tile_R_range(const int R[4], bool active, int Rl
 
 // DERIV: the call asks for the step derivatives (their sweeps need registers
 // the value alone does not, so the kernel without them is its own instance).
-template <bool BATCH, int TH, bool DERIV>
+// D: the direction frame (cluster_box.h); canon_plane[k] is the step plane of
+// the frame's k-th direction.
+template <bool BATCH, int TH, bool DERIV, int D = 0>
 __global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box(
     GatherArgs one, const GatherArgs *__restrict__ table, const int64_t *__restrict__ prefix, int B) {
     using S = FwdShape<TH>;
@@ -1040,7 +1146,7 @@ __global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box
     t.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     s_state[threadIdx.x] = cbox::pack_state(fwd_tx(threadIdx.x), fwd_ty(threadIdx.x), t.R, t.Rlo, active);
     t.state = s_state;
-    if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, S::Rows)) {
+    if (!cbox::boxes_fit<D>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, S::Rows)) {
         if (active) {
             if (a.off[6] == 1) t2n4_pixel<true>(a, t.x, t.y);
             else t2n4_pixel<false>(a, t.x, t.y);
@@ -1051,10 +1157,11 @@ __global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box
 #pragma unroll
     for (int q = 0; q < 81; ++q) J[q] = 0;
     box_stage_async<S::Waves>(
-        a, s_box, cbox::box_of<cbox::order_at(0)>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left), t.wave);
+        a, s_box, cbox::box_of<cbox::order_at(0), D>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, t.pad_left),
+        t.wave);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    box_fwd_all<0, S>(a, s_box, active, t, J);
+    box_fwd_all<0, S, D>(a, s_box, active, t, J);
     // The last kPark sums wait in the box buffers, idle now (the last
     // combination ended with a barrier), so that the epilogue's own values fit
     // in registers beside the rest; each thread reads back only its own.
@@ -1168,9 +1275,11 @@ __global__ __launch_bounds__(256) void k_gather_t2n4_fp64(GatherArgs one, const 
     if (a.out) a.out[idx] = (float)(tot / den);
 }
 
+#ifndef BSF_GATHER_FRAME1_UNIT
 // Pixel-tile shape of the kernel run_gather picks for a plan.
 struct GatherShape {
-    int kind;  // 0 int, 1 generic real, 2 tied order-2 exact, 3 tied order-2 fp64, 4 cluster boxes
+    int kind;  // 0 int, 1 generic real, 2 tied order-2 exact, 3 tied order-2 fp64, 4 cluster boxes,
+               // 5 cluster boxes of Table 1's directions
     int tile_w, tile_h;
 };
 
@@ -1181,10 +1290,14 @@ GatherShape gather_shape(const Plan &p, const GatherArgs &a) {
     } else if (p.n_dirs == 4 && p.order == 2 && p.tied && p.Hp * p.Wp * 8 < (int64_t(1) << 32)) {
         if (p.arith == BSF_ARITH_FP64) {
             s.kind = 3;
-        } else if (a.canon) {
+        } else if (a.canon == 1) {
             s.kind = 4;
             s.tile_w = kFwdTileW;
             s.tile_h = tuning().box_h;
+        } else if (a.canon == 2) {
+            s.kind = 5;
+            s.tile_w = kFwdTileW;
+            s.tile_h = 8;  // the 13-row patch needs the 38-row boxes
         } else {
             s.kind = 2;
             const bool contig = a.off[6] == 1;
@@ -1201,7 +1314,7 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
                          int64_t total_tiles, hipStream_t st) {
     const GatherShape s = gather_shape(p, one);
     dim3 grid;
-    if (s.kind == 4 || s.kind == 0 || s.kind == 1) {  // tiles in XCD order (tile_of_block_xcd)
+    if (s.kind == 4 || s.kind == 5 || s.kind == 0 || s.kind == 1) {  // tiles in XCD order (tile_of_block_xcd)
         const int64_t tiles = BATCH ? total_tiles
                                     : ((p.W + s.tile_w - 1) / s.tile_w) * ((p.H + s.tile_h - 1) / s.tile_h);
         grid = dim3((unsigned)xcd_grid(tiles));
@@ -1210,7 +1323,7 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
     } else {
         grid = dim3((unsigned)((p.W + s.tile_w - 1) / s.tile_w), (unsigned)((p.H + s.tile_h - 1) / s.tile_h));
     }
-    dim3 block(s.kind == 4 ? 16 * s.tile_h : 256);
+    dim3 block(s.kind == 4 || s.kind == 5 ? 16 * s.tile_h : 256);
     const bool fp64 = p.arith == BSF_ARITH_FP64;
     if (s.kind == 0) {
         if (p.M == 4) {
@@ -1232,6 +1345,9 @@ bsf_status launch_gather(const Plan &p, const GatherArgs &one, const GatherArgs 
             if (deriv) hipLaunchKernelGGL((k_gather_t2n4_box<false, 8, true>), grid, block, 0, st, one, table, prefix, B);
             else hipLaunchKernelGGL((k_gather_t2n4_box<BATCH, 8, false>), grid, block, 0, st, one, table, prefix, B);
         }
+    } else if (s.kind == 5) {
+        if (BATCH) return BSF_E_INVALID;  // the batched forward takes kind 2 for these directions
+        return launch_gather_f1(one, grid, block, st);
     } else if (s.kind == 2) {
         const bool contig = one.off[6] == 1;
         if (!contig) {
@@ -1320,3 +1436,16 @@ void make_bound_job(const float *steps, const float *img, int64_t H, int64_t W, 
 }
 
 }  // namespace bsf
+
+#else  // BSF_GATHER_FRAME1_UNIT: the cluster-box kernels of Table 1's directions
+}  // namespace
+
+bsf_status launch_gather_f1(const GatherArgs &a, dim3 grid, dim3 block, hipStream_t st) {
+    if (a.dsteps) hipLaunchKernelGGL((k_gather_t2n4_box<false, 8, true, 1>), grid, block, 0, st, a, nullptr, nullptr, 1);
+    else hipLaunchKernelGGL((k_gather_t2n4_box<false, 8, false, 1>), grid, block, 0, st, a, nullptr, nullptr, 1);
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
+}
+
+}  // namespace bsf
+#endif

@@ -12,8 +12,10 @@
 //     (pixel_base, and packed_base from the packed state) points to: the box
 //     element is the window element of that tap;
 //   - the packed state keeps the tile position and R_k - Rlo_k exactly.
-// Input (stdin): lines "H W R_max pad_top pad_left win_h win_w tile_w tile_h
-// rows cases seed"; prints "ok <fitting tiles> <taps checked>" or the first
+// Both direction frames are checked (frame 0: (1,0), (0,1), (1,1), (1,-1);
+// frame 1: (2,1), (1,2), (1,-2), (2,-1)).
+// Input (stdin): lines "frame H W R_max pad_top pad_left win_h win_w tile_w
+// tile_h rows cases seed"; prints "ok <fitting tiles> <taps checked>" or the first
 // failure, and exits non-zero on failure.
 #include <cstdio>
 #include <cstdlib>
@@ -41,7 +43,7 @@ bool fail(const char *what, long a, long b) {
     return false;
 }
 
-const int kU[4][2] = {{1, 0}, {0, 1}, {1, 1}, {1, -1}};
+const int kU[2][4][2] = {{{1, 0}, {0, 1}, {1, 1}, {1, -1}}, {{2, 1}, {1, 2}, {1, -2}, {2, -1}}};
 
 bool check_clusters(int R) {
     std::multiset<int> d2, cl;
@@ -58,10 +60,10 @@ bool check_clusters(int R) {
     return true;
 }
 
-template <int C>
+template <int D, int C>
 bool check_combo(const Geom &g, int x_lo, int x_hi, int y_lo, int y_hi, const int Rlo[4], const int Rhi[4],
                  const int (*R)[4], const bool *active) {
-    const cbox::Box b = cbox::box_of<C>(x_lo, x_hi, y_lo, y_hi, Rlo, Rhi, (int)g.pad_left);
+    const cbox::Box b = cbox::box_of<C, D>(x_lo, x_hi, y_lo, y_hi, Rlo, Rhi, (int)g.pad_left);
     if ((b.ox + g.pad_left) % 2 != 0) return fail("box start column parity", b.ox + g.pad_left, 0);
     if (b.bw > cbox::kPitch) return fail("box width", b.bw, cbox::kPitch);
     if (b.bh > g.rows) return fail("box rows", b.bh, g.rows);
@@ -78,12 +80,12 @@ bool check_combo(const Geom &g, int x_lo, int x_hi, int y_lo, int y_hi, const in
             for (int k = 0; k < 4; ++k)
                 if ((int)((st >> (10 + 5 * k)) & 31u) != R[i][k] - Rlo[k])
                     return fail("packed R", (st >> (10 + 5 * k)) & 31u, R[i][k] - Rlo[k]);
-            const int base = cbox::pixel_base<C>(x, y, R[i], b);
-            const int pbase = cbox::packed_base<C>(st, x_lo, y_lo, Rlo, b);
+            const int base = cbox::pixel_base<C, D>(x, y, R[i], b);
+            const int pbase = cbox::packed_base<C, D>(st, x_lo, y_lo, Rlo, b);
             if (base != pbase) return fail("packed_base", pbase, base);
             for (int q = 0; q < 81; ++q) {
                 const int q0 = q % 3, q1 = (q / 3) % 3, q2 = (q / 9) % 3, q3 = q / 27;
-                const int e = base + cbox::sub_elem(q0, q1, q2, q3);
+                const int e = base + cbox::sub_elem<D>(q0, q1, q2, q3);
                 if (e < 0) return fail("negative LDS element", e, 0);
                 const int row = e / cbox::kPitch, col = e % cbox::kPitch;
                 if (row >= b.bh || col >= b.bw) return fail("tap outside its box", row, col);
@@ -91,8 +93,8 @@ bool check_combo(const Geom &g, int x_lo, int x_hi, int y_lo, int y_hi, const in
                 long tx_img = x, ty_img = y;
                 for (int k = 0; k < 4; ++k) {
                     const int m = cbox::base_of(cbox::cl(C, k), R[i][k]) + qs[k];
-                    tx_img += (long)m * kU[k][0];
-                    ty_img += (long)m * kU[k][1];
+                    tx_img += (long)m * kU[D][k][0];
+                    ty_img += (long)m * kU[D][k][1];
                 }
                 if (b.ox + col != tx_img || b.oy + row != ty_img) return fail("box element is not the tap", tx_img, ty_img);
                 ++g_taps;
@@ -101,10 +103,10 @@ bool check_combo(const Geom &g, int x_lo, int x_hi, int y_lo, int y_hi, const in
     return true;
 }
 
-template <int... Cs>
+template <int D, int... Cs>
 bool check_all(std::integer_sequence<int, Cs...>, const Geom &g, int x_lo, int x_hi, int y_lo, int y_hi,
                const int Rlo[4], const int Rhi[4], const int (*R)[4], const bool *active) {
-    return (check_combo<Cs>(g, x_lo, x_hi, y_lo, y_hi, Rlo, Rhi, R, active) && ...);
+    return (check_combo<D, Cs>(g, x_lo, x_hi, y_lo, y_hi, Rlo, Rhi, R, active) && ...);
 }
 
 }  // namespace
@@ -116,8 +118,10 @@ int main() {
     long fitting = 0;
     for (int R = 0; R < 200; ++R)
         if (!check_clusters(R)) return 1;
-    while (std::scanf("%ld %ld %d %ld %ld %ld %ld %d %d %d %d %u", &g.H, &g.W, &g.R_max, &g.pad_top, &g.pad_left,
-                      &g.win_h, &g.win_w, &g.tile_w, &g.tile_h, &g.rows, &cases, &seed) == 12) {
+    int frame;
+    while (std::scanf("%d %ld %ld %d %ld %ld %ld %ld %d %d %d %d %u", &frame, &g.H, &g.W, &g.R_max, &g.pad_top,
+                      &g.pad_left, &g.win_h, &g.win_w, &g.tile_w, &g.tile_h, &g.rows, &cases, &seed) == 13) {
+        if (frame != 0 && frame != 1) return fail("frame", frame, 0), 1;
         std::mt19937 rng(seed);
         const long tiles_x = (g.W + g.tile_w - 1) / g.tile_w, tiles_y = (g.H + g.tile_h - 1) / g.tile_h;
         static int R[256][4];
@@ -132,7 +136,7 @@ int main() {
             const int y_hi = (int)std::min<long>(y_lo + g.tile_h - 1, g.H - 1);
             int Rlo[4], Rhi[4];
             for (int k = 0; k < 4; ++k) {
-                const int spread = (int)(rng() % 13);
+                const int spread = (rng() % 2) ? (int)(rng() % 13) : (int)(rng() % 3);
                 Rlo[k] = (int)(rng() % (g.R_max + 1));
                 Rhi[k] = std::min(Rlo[k] + spread, g.R_max);
             }
@@ -147,12 +151,18 @@ int main() {
             }
             active[0] = true;
             active[(x_hi - x_lo) + (y_hi - y_lo) * g.tile_w] = true;
-            if (!cbox::boxes_fit(x_lo, x_hi, y_lo, y_hi, Rlo, Rhi, g.rows)) continue;
+            const bool fits = frame == 0 ? cbox::boxes_fit<0>(x_lo, x_hi, y_lo, y_hi, Rlo, Rhi, g.rows)
+                                         : cbox::boxes_fit<1>(x_lo, x_hi, y_lo, y_hi, Rlo, Rhi, g.rows);
+            if (!fits) continue;
             ++fitting;
-            if (!check_all(std::make_integer_sequence<int, cbox::kCombos>{}, g, x_lo, x_hi, y_lo, y_hi, Rlo, Rhi, R,
-                           active)) {
-                std::printf("case H=%ld W=%ld Rmax=%d tile %dx%d rows %d at (%d,%d) Rlo %d %d %d %d Rhi %d %d %d %d\n",
-                            g.H, g.W, g.R_max, g.tile_w, g.tile_h, g.rows, x_lo, y_lo, Rlo[0], Rlo[1], Rlo[2],
+            const bool ok =
+                frame == 0 ? check_all<0>(std::make_integer_sequence<int, cbox::kCombos>{}, g, x_lo, x_hi, y_lo, y_hi,
+                                          Rlo, Rhi, R, active)
+                           : check_all<1>(std::make_integer_sequence<int, cbox::kCombos>{}, g, x_lo, x_hi, y_lo, y_hi,
+                                          Rlo, Rhi, R, active);
+            if (!ok) {
+                std::printf("frame %d case H=%ld W=%ld Rmax=%d tile %dx%d rows %d at (%d,%d) Rlo %d %d %d %d Rhi %d %d %d %d\n",
+                            frame, g.H, g.W, g.R_max, g.tile_w, g.tile_h, g.rows, x_lo, y_lo, Rlo[0], Rlo[1], Rlo[2],
                             Rlo[3], Rhi[0], Rhi[1], Rhi[2], Rhi[3]);
                 return 1;
             }

@@ -1,7 +1,8 @@
 """Host check of the cluster-box index arithmetic of the tied order-2 gather
 and adjoint kernels (cluster_box.h): tests/cbox_check.cpp walks box_of,
 pixel_base, pack_state / packed_base and boxes_fit over random tiles, step
-ranges and the window geometries bsf_plan gives, and checks that every
+ranges and the window geometries bsf_plan gives, in both direction frames
+(Section 1.1's set and the set of Table 1), and checks that every
 sub-tap a pixel reads from its LDS box is the window element of that tap, that
 every accepted box fits the LDS box and the window (with the spare column of
 the pair copies), and that the nine taps per direction are those of the
@@ -33,19 +34,22 @@ def checker(tmp_path_factory):
 # a one-row image, and steps large enough that few tiles fit
 GEOMS = [(4096, 4096, 48.0), (37, 53, 9.0), (300, 17, 21.0), (1, 64, 15.0), (129, 2000, 63.0),
          (1024, 1024, 20.0)]
-# (tile_w, tile_h, LDS rows): the forward kernel's 16 x 8 tiles with 38-row
-# boxes and the adjoint's 16 x 16 tiles with 48-row boxes
-TILES = [(16, 8, 38), (16, 16, 48)]
+# (frame, tile_w, tile_h, LDS rows): the forward kernel's 16 x 8 tiles with
+# 38-row boxes and 16 x 4 tiles with 18-row boxes, the adjoint's 16 x 16 tiles
+# with 48-row boxes; in the frame of Table 1's directions the forward's 16 x 8
+# tiles
+TILES = [(0, 16, 8, 38), (0, 16, 4, 18), (0, 16, 16, 48), (1, 16, 8, 38)]
+DIRS = {0: ((1, 0), (0, 1), (1, 1), (1, -1)), 1: ((2, 1), (1, 2), (1, -2), (2, -1))}
 
 
 def test_cluster_box_indexing(checker):
     lines = []
     for n, (H, W, ms) in enumerate(GEOMS):
-        g = bsf.plan(bsf.Config(order=2, max_step=ms), H, W)
         R_max = int((ms - 1) // 2)
-        for tw, th, rows in TILES:
-            lines.append("%d %d %d %d %d %d %d %d %d %d %d %d" % (H, W, R_max, g.pad_top, g.pad_left, g.win_h,
-                                                                  g.win_w, tw, th, rows, 200, 1000 + n))
+        for frame, tw, th, rows in TILES:
+            g = bsf.plan(bsf.Config(dirs=DIRS[frame], order=2, max_step=ms), H, W)
+            lines.append("%d %d %d %d %d %d %d %d %d %d %d %d %d" % (frame, H, W, R_max, g.pad_top, g.pad_left,
+                                                                     g.win_h, g.win_w, tw, th, rows, 200, 1000 + n))
     p = subprocess.run([checker], input="\n".join(lines) + "\n", capture_output=True, text=True, timeout=300)
     assert p.returncode == 0, p.stdout + p.stderr
     words = p.stdout.split()

@@ -67,6 +67,20 @@ def test_gradients_match_oracle(order, tied, shape, hi, smooth):
     assert_grad_close(gs, rgs, what="grad_steps")
 
 
+def test_gradients_table1_directions():
+    """Step derivatives from the cluster-box kernel in the frame of Table 1's
+    directions, and the image gradient of the generic scatter, against the
+    oracle's analytic gradients."""
+    note("adjoint table1 directions")
+    dirs = ((2, 1), (1, 2), (1, -2), (2, -1))
+    img, steps, g = case((44, 52), 4, 1.0, 11.0, 71, smooth=True)
+    cfg = bsf.Config(dirs=dirs, order=2, max_step=11.0)
+    out, gi, gs, ds = gpu_grads(cfg, img, steps, g)
+    rgi, rgs = O.grad_real(img, dirs, 2, True, steps, g)
+    assert_grad_close(gi, rgi, what="grad_img")
+    assert_grad_close(gs, rgs, what="grad_steps")
+
+
 def test_dot_product_identity_on_gpu():
     """<K f, g> = <f, K^T g> with the GPU forward and the GPU adjoint."""
     note("dot product")

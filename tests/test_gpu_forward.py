@@ -162,6 +162,32 @@ def test_alg3_directions(order, mode, shape, hi):
     assert_close(out, ref, F, quantised=mode != "int", what="alg3 directions")
 
 
+@pytest.mark.parametrize("shape,hi,smooth", [
+    ((96, 112), 14.0, True),     # most tiles take the cluster boxes
+    ((61, 77), 12.0, False),     # independent steps: most tiles read the window directly
+    ((9, 200), 6.0, True),       # one ragged row of tiles
+    ((40, 33), 3.0, False),      # small steps, every tile fits
+])
+def test_table1_directions_tied_order2_every_pixel(shape, hi, smooth):
+    """The tied order-2 cluster-box kernel in the frame of Table 1's
+    directions, given in another order than its own frame: every pixel against
+    the oracle (tiles whose step range does not fit the LDS boxes read the
+    window directly)."""
+    note("table1 cluster boxes", shape, smooth)
+    dirs = ((1, -2), (2, 1), (2, -1), (1, 2))
+    rng = np.random.default_rng(60 + shape[0])
+    img = rng.random(shape, dtype=np.float32)
+    if smooth:
+        steps = np.stack([WL.smooth(rng, *shape, 1.0, hi) for _ in range(4)]).astype(np.float32)
+    else:
+        steps = rand_steps(shape, 4, 1.0, hi, 61)
+    cfg = bsf.Config(dirs=dirs, order=2, max_step=hi)
+    out, _, _, flags, F = run_forward(cfg, img, steps)
+    ref = O.filter(img, dirs, 2, True, O.REAL, steps)
+    assert flags == 0
+    assert_close(out, ref, F, what="table1 tied order2")
+
+
 def test_continuous_untied_order2_generic():
     note("real untied order2")
     shape = (12, 14)
