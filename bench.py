@@ -51,7 +51,7 @@ def measured_traffic(box_h):
             h.update(fh.read())
     if h.hexdigest() != rec.get("sha256"):
         return None
-    entry = rec.get("kernels", {}).get("k_gather_t2n4_box<false, %d, false>" % box_h)
+    entry = rec.get("kernels", {}).get("k_gather_t2n4_box<false, %d, false, 0>" % box_h)
     return None if entry is None else entry.get("bytes_per_launch")
 
 
@@ -98,7 +98,8 @@ def main():
     ap.add_argument("--alg3-steps", type=int, default=5)
     ap.add_argument("--alg2-size", type=int, default=4096, help="Alg. 2 workload side (0: skip)")
     ap.add_argument("--alg2-steps", type=int, default=3)
-    ap.add_argument("--alg2-order", type=int, default=1, help="order of Alg. 2's box splines (the paper's is 1)")
+    ap.add_argument("--alg2-orders", default="1,2",
+                    help="orders of Alg. 2's box splines, comma-separated (the paper's is 1)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, one device copy of this size (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -350,16 +351,18 @@ def main():
     # of the second set at 10-15 %)
     alg2 = None
     if args.alg2_size > 0:
+        alg2 = []
         d2 = WL.workload_alg3(args.alg2_size, args.alg2_size)
         H2, W2 = d2["img"].shape
         img2 = torch.from_numpy(d2["img"]).to(dev)
         cov2 = torch.from_numpy(d2["cov"]).to(dev)
+    for order2 in ([int(o) for o in args.alg2_orders.split(",") if o] if args.alg2_size > 0 else []):
         # max_step from the data: the largest step either set needs for this field
         smax = 1.0
         for dirs in (((1, 0), (0, 1), (1, 1), (1, -1)), WL.DIRS_TABLE1):
-            probe = bsf.Config(dirs=dirs, order=args.alg2_order, tied=True, mode=bsf.STEPS_REAL, max_step=1e5)
+            probe = bsf.Config(dirs=dirs, order=order2, tied=True, mode=bsf.STEPS_REAL, max_step=1e5)
             smax = max(smax, float(bsf.cov_to_steps(probe, cov2).max().item()))
-        cfg2 = bsf.Config(order=args.alg2_order, tied=True, mode=bsf.STEPS_REAL, max_step=float(np.ceil(smax)))
+        cfg2 = bsf.Config(order=order2, tied=True, mode=bsf.STEPS_REAL, max_step=float(np.ceil(smax)))
         ws2 = bsf.Workspace(bsf.lib().bsf_alg2_workspace_bytes(bsf.ctypes.byref(cfg2.c()), H2, W2), dev)
         bank2 = torch.empty((H2, W2), dtype=torch.uint8, device=dev)
         out2 = torch.empty((H2, W2), dtype=torch.float32, device=dev)
@@ -388,13 +391,15 @@ def main():
             return float(np.median(t))
         ms_two, ms_one = timed(two_sets), timed(one_set)
         frac2 = float(bank2.float().mean().item())
-        alg2 = {"workload": "%dx%d covariance field (sigma 2-12 px), order %d, max_step %g"
-                            % (H2, W2, args.alg2_order, cfg2.max_step),
-                "ms_two_sets": ms_two, "ms_one_set": ms_one, "cost_ratio": ms_two / ms_one,
-                "pixels_on_second_set": frac2, "steps": args.alg2_steps}
-        log("alg2 %dx%d: two sets %.3f ms, one set %.3f ms (x%.2f), %.0f%% of pixels on the second"
-            % (H2, W2, ms_two, ms_one, ms_two / ms_one, 100 * frac2))
-        del img2, cov2, ws2, bank2, out2, steps1, ws1
+        alg2.append({"workload": "%dx%d covariance field (sigma 2-12 px), order %d, max_step %g"
+                                 % (H2, W2, order2, cfg2.max_step),
+                     "order": order2, "ms_two_sets": ms_two, "ms_one_set": ms_one, "cost_ratio": ms_two / ms_one,
+                     "pixels_on_second_set": frac2, "steps": args.alg2_steps})
+        log("alg2 %dx%d order %d: two sets %.3f ms, one set %.3f ms (x%.2f), %.0f%% of pixels on the second"
+            % (H2, W2, order2, ms_two, ms_one, ms_two / ms_one, 100 * frac2))
+        del ws2, bank2, out2, steps1, ws1
+    if args.alg2_size > 0:
+        del img2, cov2
 
     # ---- integer steps on a uint8 image: exact int64 numerator and prod s
     integer = None

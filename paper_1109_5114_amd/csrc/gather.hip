@@ -1138,6 +1138,9 @@ __global__ __launch_bounds__(64 * FwdShape<TH>::Waves, 2) void k_gather_t2n4_box
         if (active) report_steps(a, bad, prod);
     }
     tile_R_range<S::Waves>(t.R, active, t.Rlo, t.Rhi);
+    // no pixel of the tile to filter (outside the image, or in Alg. 2 on the
+    // other direction set): the range is empty and the tile is done
+    if (t.Rlo[0] > t.Rhi[0]) return;
     t.x_lo = (int)(bx * kFwdTileW);
     t.y_lo = (int)(by * TH);
     t.x_hi = (int)min((int64_t)t.x_lo + kFwdTileW - 1, a.W - 1);
