@@ -409,6 +409,10 @@ def main():
         cfg3 = bsf.Config(dirs=d3["dirs"], order=1, tied=True, mode=bsf.STEPS_INT, max_step=d3["max_step"])
         img3 = torch.from_numpy(d3["img"]).to(dev)
         steps3 = torch.from_numpy(d3["steps"]).to(dev)
+        # launch shapes for this workload (its image is smaller: shorter line
+        # tiles give its scans more parallel work); the workspace size depends
+        # on them, so it is sized after
+        tuning3 = None if args.no_tune else tuner.tune(cfg3, H3, W3, dev, img=img3, steps=steps3)
         ws3 = bsf.Workspace(bsf.plan(cfg3, H3, W3).workspace_bytes, dev)
         out3 = torch.empty((H3, W3), dtype=torch.float32, device=dev)
         num3 = torch.empty((H3, W3), dtype=torch.int64, device=dev)
@@ -440,6 +444,7 @@ def main():
         g3 = bsf.plan(cfg3, H3, W3)
         tap_bytes = H3 * W3 * (16 + 4 + 8 + 8) + g3.g_bytes
         integer = {"workload": d3["name"], "ms_per_step": p3 + a3, "prepare_ms": p3, "apply_ms": a3,
+                   "tuning": None if tuning3 is None else {k: tuning3[k] for k in ("gather_wx", "line_tl", "box_h")},
                    "value": H3 * W3 / ((p3 + a3) / 1e3) / 1e6, "unit": "Mpixels/s",
                    "apply_hbm_gbs": tap_bytes / (a3 / 1e3) / 1e9,
                    "apply_hbm_frac": tap_bytes / (a3 / 1e3) / 1e9 / HBM_PEAK_GBS,

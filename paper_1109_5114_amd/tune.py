@@ -128,8 +128,11 @@ def tune(cfg: Config, H: int, W: int, device="cuda", reps: int = 3, cache: Optio
         canonical = sorted(map(tuple, cfg.dirs)) == sorted(((1, 0), (0, 1), (1, 1), (1, -1)))
         t2n4 = cfg.mode != STEPS_INT and cfg.order == 2 and cfg.tied and cfg.n_dirs == 4 \
             and cfg.arith == ARITH_EXACT
+        table1 = sorted(map(tuple, cfg.dirs)) == sorted(((2, 1), (1, 2), (1, -2), (2, -1)))
         if t2n4 and canonical:
             shapes = [(old[0], h) for h in box_h]
+        elif t2n4 and table1:
+            shapes = [(old[0], old_h)]   # its cluster-box kernel has one tile shape
         elif t2n4:
             shapes = [(wx, old_h) for wx in gather_wx]
         else:
