@@ -106,3 +106,56 @@ def test_alg1_is_one_filter_of_covariance_C():
     # whose covariance is the same; each continuous box adds the unit-cell
     # term (1 - lambda)lambda-type excess, below 1/4 per direction and pass
     assert np.abs(m - C).max() < 1.5, (m, C)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_alg2_full_size_sampled(order):
+    """Alg. 2 on the 4096 x 4096 covariance-field workload (orientation,
+    elongation 1-6 and size 2-12 px from smooth fields): the sector of
+    sampled pixels against the oracle's rule, and sampled outputs against the
+    oracle's filter of the sector's direction set on crops that hold each
+    pixel's footprint (outside it the filter reads nothing), with the steps
+    bsf_cov_to_steps gives for that set.  At order 2 the taps of both sets come
+    from their cluster-box kernels (and the direct reads of tiles whose boxes
+    do not fit)."""
+    d = WL.workload_alg3()
+    img, cov = d["img"], d["cov"]
+    H, W = img.shape
+    note("alg2 full size order", order, H, W)
+    tcov = to_dev(cov)
+    smax = 1.0
+    for dirs in (O.BANK1, O.BANK2):
+        probe = bsf.Config(dirs=dirs, order=order, max_step=1e5)
+        smax = max(smax, float(bsf.cov_to_steps(probe, tcov).max().item()))
+    cfg = bsf.Config(order=order, max_step=float(np.ceil(smax)))
+    ws = bsf.Workspace(bsf.lib().bsf_alg2_workspace_bytes(bsf.ctypes.byref(cfg.c()), H, W), DEV)
+    bank = torch.empty((H, W), dtype=torch.uint8, device=DEV)
+    out = bsf.filter_alg2(cfg, to_dev(img), tcov, bank=bank, ws=ws).cpu().numpy()
+    flags, F, _ = read_status(ws)
+    assert flags & ~bsf.FLAG_RANGE == 0
+    assert np.isfinite(out).all()
+    bank = bank.cpu().numpy()
+    rng = np.random.default_rng(450 + order)
+    ys, xs = rng.integers(0, H, 3000), rng.integers(0, W, 3000)
+    want = [O.bank_of(O.orientation(float(cov[0, y, x]), float(cov[1, y, x]), float(cov[2, y, x])))
+            for y, x in zip(ys, xs)]
+    np.testing.assert_array_equal(bank[ys, xs], np.array(want, np.uint8))
+    assert 0.2 < bank.mean() < 0.8
+    # the steps each set's filter uses (clamped to [1, max_step] as the kernels do)
+    steps = []
+    for dirs in (O.BANK1, O.BANK2):
+        st = bsf.cov_to_steps(bsf.Config(dirs=dirs, order=order, max_step=cfg.max_step), tcov).cpu().numpy()
+        steps.append(np.where(np.isfinite(st), np.clip(st, 1.0, cfg.max_step), 1.0).astype(np.float32))
+    pts = [(0, 0), (W - 1, H - 1), (0, H - 1), (W - 1, 0)] + [tuple(p) for p in rng.integers(0, [W, H], (40, 2))]
+    for x, y in pts:
+        b = int(bank[y, x])
+        dirs, st = (O.BANK1, O.BANK2)[b], steps[b]
+        R = np.floor((st[:, y, x].astype(np.float64) - 1.0) / 2.0)
+        rx = int(sum(order * (r + 2) * abs(u[0]) for u, r in zip(dirs, R))) + 2
+        ry = int(sum(order * (r + 2) * abs(u[1]) for u, r in zip(dirs, R))) + 2
+        x0, x1, y0, y1 = max(0, x - rx), min(W, x + rx + 1), max(0, y - ry), min(H, y + ry + 1)
+        crop = np.ascontiguousarray(img[y0:y1, x0:x1])
+        cst = np.ascontiguousarray(st[:, y0:y1, x0:x1])
+        ref = O.filter(crop, dirs, order, True, O.REAL, cst, pix=np.array([(y - y0) * (x1 - x0) + (x - x0)]))[0]
+        tol = 2.0 ** -(F + 1) + 2.0 ** -24 * abs(ref) * 1.01 + 1e-13
+        assert abs(float(out[y, x]) - ref) <= tol, (x, y, b, float(out[y, x]), ref, tol)
