@@ -167,6 +167,8 @@ def test_alg3_directions(order, mode, shape, hi):
     ((61, 77), 12.0, False),     # independent steps: most tiles read the window directly
     ((9, 200), 6.0, True),       # one ragged row of tiles
     ((40, 33), 3.0, False),      # small steps, every tile fits
+    ((1, 1), 4.0, False),        # one pixel
+    ((5, 3), 7.0, False),        # smaller than one tile
 ])
 def test_table1_directions_tied_order2_every_pixel(shape, hi, smooth):
     """The tied order-2 cluster-box kernel in the frame of Table 1's
