@@ -14,6 +14,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "bsf_common.h"
 
 namespace bsf {
@@ -158,6 +160,34 @@ bsf_status one_pass(const Plan &p, int src_kind, int32_t frac_bits, const void *
     return run_gather(p, a, st);
 }
 
+// A second stream per device, on which Alg. 2 runs its second direction set
+// beside the first: forked from the caller's stream and joined back into it by
+// events (graph capture follows the fork and the join too).  Created on the
+// first call on a device and kept for the process, at the default priority.
+// The lock keeps the record / wait pairs of concurrent calls from
+// interleaving.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_side_lock;
+SideStream g_side[kMaxDevices];
+
+bsf_status side_stream_locked(SideStream *&out) {
+    int dev = 0;
+    BSF_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return BSF_E_UNSUPPORTED;
+    SideStream &ss = g_side[dev];
+    if (!ss.s) {
+        BSF_HIP_CHECK(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+        BSF_HIP_CHECK(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
+        BSF_HIP_CHECK(hipEventCreateWithFlags(&ss.join, hipEventDisableTiming));
+    }
+    out = &ss;
+    return BSF_OK;
+}
+
 int src_kind(bsf_dtype d) { return d == BSF_U8 ? SRC_U8 : d == BSF_U16 ? SRC_U16 : d == BSF_F32 ? SRC_F32 : -1; }
 
 bsf_config with_dirs(const bsf_config &c, const int dirs[8]) {
@@ -293,10 +323,23 @@ bsf_status bsf_filter_alg2(const bsf_config *cfg, bsf_dtype dtype, const void *i
     // sector, scales of the pixel's own box spline; the other set's steps are 1
     r = run_cov_to_steps(p1, b1, &b2, cov, nullptr, 0.0f, L.steps1, L.steps2, sel, L.top, st);
     if (r != BSF_OK) return r;
-    r = one_pass(p1, kind, cfg->frac_bits, img, pitch, L.steps1, out, sel, 0, L.ws1, st);
-    if (r != BSF_OK) return r;
-    r = one_pass(p2, kind, cfg->frac_bits, img, pitch, L.steps2, out, sel, 1, L.ws2, st);
-    if (r != BSF_OK) return r;
+    // the two sets' passes touch disjoint workspace regions and output pixels:
+    // the second runs on the side stream while the first runs on st
+    {
+        std::lock_guard<std::mutex> lock(g_side_lock);
+        SideStream *ss = nullptr;
+        r = side_stream_locked(ss);
+        if (r != BSF_OK) return r;
+        BSF_HIP_CHECK(hipEventRecord(ss->fork, st));
+        BSF_HIP_CHECK(hipStreamWaitEvent(ss->s, ss->fork, 0));
+        r = one_pass(p2, kind, cfg->frac_bits, img, pitch, L.steps2, out, sel, 1, L.ws2, ss->s);
+        const bsf_status r1 = one_pass(p1, kind, cfg->frac_bits, img, pitch, L.steps1, out, sel, 0, L.ws1, st);
+        // join even when a launch failed, so that st never runs ahead of work on the side stream
+        BSF_HIP_CHECK(hipEventRecord(ss->join, ss->s));
+        BSF_HIP_CHECK(hipStreamWaitEvent(st, ss->join, 0));
+        if (r != BSF_OK) return r;
+        if (r1 != BSF_OK) return r1;
+    }
     hipLaunchKernelGGL(k_alg_merge, dim3(1), dim3(64), 0, st, L.top, s1, s2);
     BSF_HIP_CHECK(hipGetLastError());
     return BSF_OK;
