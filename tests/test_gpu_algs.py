@@ -159,3 +159,35 @@ def test_alg2_full_size_sampled(order):
         ref = O.filter(crop, dirs, order, True, O.REAL, cst, pix=np.array([(y - y0) * (x1 - x0) + (x - x0)]))[0]
         tol = 2.0 ** -(F + 1) + 2.0 ** -24 * abs(ref) * 1.01 + 1e-13
         assert abs(float(out[y, x]) - ref) <= tol, (x, y, b, float(out[y, x]), ref, tol)
+
+
+def test_alg2_in_a_captured_graph():
+    """Alg. 2 runs its second direction set on a side stream, forked from and
+    joined back into the caller's stream by events: captured into a graph on
+    the caller's stream, every replay (with eager work between them) gives
+    the eager call's output and sectors."""
+    note("alg2 graph capture")
+    rng = np.random.default_rng(470)
+    H, W = 64, 80
+    img = to_dev(rng.random((H, W), dtype=np.float32))
+    cov = to_dev(cov_field(rng, H, W, rho_max=5.0, bank=2))
+    cfg = bsf.Config(order=2, max_step=80.0)
+    ws = bsf.Workspace(bsf.lib().bsf_alg2_workspace_bytes(bsf.ctypes.byref(cfg.c()), H, W), DEV)
+    out = torch.empty((H, W), dtype=torch.float32, device=DEV)
+    bank = torch.empty((H, W), dtype=torch.uint8, device=DEV)
+    bsf.filter_alg2(cfg, img, cov, out=out, bank=bank, ws=ws)   # eager: also makes the side stream
+    torch.cuda.synchronize()
+    ref, ref_bank = out.clone(), bank.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        bsf.filter_alg2(cfg, img, cov, out=out, bank=bank, ws=ws)
+    for rep in range(3):
+        out.fill_(-1.0)
+        bank.fill_(7)
+        junk = torch.randn(256, 256, device=DEV) @ torch.randn(256, 256, device=DEV)   # eager work between
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        assert torch.equal(bank, ref_bank), rep
+    del junk
