@@ -327,6 +327,11 @@ bsf_status bsf_filter_alg1(const bsf_config *cfg, const float *img, int64_t H, i
  *   bank_out: nullable uint8 [H][W]: 0 or 1, the set each pixel used.
  *   ws:       at least bsf_alg2_workspace_bytes (status block first: flags of
  *             both sets, the smaller F).
+ *   stream:   the second set's pass runs on a library-owned stream of the
+ *             current device (created on the first call, default priority),
+ *             forked from and joined back into this stream by events, so the
+ *             call is ordered on `stream` as a whole and can be captured into a
+ *             graph on it.
  */
 size_t bsf_alg2_workspace_bytes(const bsf_config *cfg, int64_t H, int64_t W);
 bsf_status bsf_filter_alg2(const bsf_config *cfg, bsf_dtype dtype, const void *img, int64_t H, int64_t W,
