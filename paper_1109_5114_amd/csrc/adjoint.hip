@@ -32,6 +32,12 @@
 #include "cluster_box.h"
 
 namespace bsf {
+
+// The cluster-box scatter in the frame of Table 1's directions (canon = 2),
+// launched on the given grid; defined by adjoint_f1.hip, which compiles this
+// file's kernels for that frame only.
+bsf_status launch_adj_scatter_f1(const AdjointArgs &a, dim3 grid, hipStream_t st);
+
 namespace {
 
 constexpr int kTile = 16;
@@ -331,7 +337,7 @@ __global__ __launch_bounds__(256) void k_adj_scatter_t2n4(AdjointArgs a) {
 
 // ----------------------------------------------------------------------------
 // The same scatter through LDS cluster boxes (directions (1,0), (0,1), (1,1),
-// (1,-1)).  A 16 x 16 tile visits the 81 cluster combinations; for each,
+// (1,-1), or those of Table 1 in the frame of cluster_box.h).  A 16 x 16 tile visits the 81 cluster combinations; for each,
 // every pixel adds its sub-patch weights, summed per distinct point, into the
 // combination's box in LDS, and after one barrier the box is added to the
 // window with row-contiguous atomics and cleared.  Two LDS boxes alternate,
@@ -386,6 +392,36 @@ __device__ __forceinline__ void box_adj_points(uint64_t *__restrict__ p, const u
     if constexpr (P + 1 < 49) box_adj_points<C, P + 1>(p, W);
 }
 
+// Frame 1 (the directions of Table 1): the sub-taps at each point X + 13 Y
+// of the 13 x 13 patch (at most two share a point), and one LDS atomic per
+// point hit, points in row order.
+struct F1Patch {
+    int count[13 * 13];
+    int q[13 * 13][2];
+};
+__host__ __device__ constexpr F1Patch make_f1_patch() {
+    F1Patch t{};
+    for (int q = 0; q < 81; ++q) {
+        const int q0 = q % 3, q1 = (q / 3) % 3, q2 = (q / 9) % 3, q3 = q / 27;
+        const int P = cbox::sub_dx<1>(q0, q1, q2, q3) + 13 * cbox::sub_row<1>(q0, q1, q2, q3);
+        t.q[P][t.count[P]++] = q;
+    }
+    return t;
+}
+constexpr F1Patch kF1Patch = make_f1_patch();
+static_assert(cbox::patch_w<1>() == 13 && cbox::patch_h<1>() == 13, "frame 1 patch");
+
+template <int C, int P>
+__device__ __forceinline__ void box_adj_points_f1(uint64_t *__restrict__ p, const uint64_t W[81]) {
+    if constexpr (kF1Patch.count[P] > 0) {
+        uint64_t v = sub_weight<C, kF1Patch.q[P][0]>(W);
+        if constexpr (kF1Patch.count[P] > 1) v += sub_weight<C, kF1Patch.q[P][1]>(W);
+        __hip_atomic_fetch_add(p + (P % 13) + cbox::kPitch * (P / 13), v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    if constexpr (P + 1 < 13 * 13) box_adj_points_f1<C, P + 1>(p, W);
+}
+
 struct AdjTile {
     int x, y;
     int R[4];
@@ -410,11 +446,11 @@ __device__ __forceinline__ void box_flush(const AdjointArgs &a, uint64_t *__rest
     }
 }
 
-template <int I>
+template <int I, int D>
 __device__ __forceinline__ void box_adj_all(const AdjointArgs &a, uint64_t *__restrict__ s_box, bool active,
                                             const AdjTile &t, uint64_t W[81]) {
     constexpr int C = cbox::order_at(I);
-    const cbox::Box b = cbox::box_of<C>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, (int)a.pad_left);
+    const cbox::Box b = cbox::box_of<C, D>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi, (int)a.pad_left);
     if constexpr (I == cbox::kEven) {
 #pragma unroll
         for (int q = 0; q < 81; ++q) W[q] = 0 - W[q];
@@ -424,12 +460,19 @@ __device__ __forceinline__ void box_adj_all(const AdjointArgs &a, uint64_t *__re
 #pragma unroll
     for (int q = 0; q < 81; ++q) asm volatile("" : "+v"(W[q]));
     uint64_t *buf = s_box + (I & 1) * cbox::kElems;
-    if (active) box_adj_points<C, 0>(buf + cbox::packed_base<C>(t.packed, t.x_lo, t.y_lo, t.Rlo, b), W);
+    if (active) {
+        uint64_t *p = buf + cbox::packed_base<C, D>(t.packed, t.x_lo, t.y_lo, t.Rlo, b);
+        if constexpr (D == 0) box_adj_points<C, 0>(p, W);
+        else box_adj_points_f1<C, 0>(p, W);
+    }
     __syncthreads();  // box complete; the other buffer was flushed before the previous barrier
     box_flush(a, buf, b);
-    if constexpr (I + 1 < cbox::kCombos) box_adj_all<I + 1>(a, s_box, active, t, W);
+    if constexpr (I + 1 < cbox::kCombos) box_adj_all<I + 1, D>(a, s_box, active, t, W);
 }
 
+// D: the direction frame (cluster_box.h); canon_plane[k] is the step plane of
+// the frame's k-th direction.
+template <int D>
 __global__ __launch_bounds__(256, 2) void k_adj_scatter_t2n4_box(AdjointArgs a) {
     __shared__ uint64_t s_box[2 * cbox::kElems];
     const int64_t tiles_x = (a.W + cbox::kTile - 1) / cbox::kTile, tiles_y = (a.H + cbox::kTile - 1) / cbox::kTile;
@@ -491,7 +534,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_scatter_t2n4_box(AdjointArgs a) 
     t.y_lo = (int)(by * cbox::kTile);
     t.x_hi = (int)min((int64_t)t.x_lo + cbox::kTile - 1, a.W - 1);
     t.y_hi = (int)min((int64_t)t.y_lo + cbox::kTile - 1, a.H - 1);
-    if (!cbox::boxes_fit(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi)) {
+    if (!cbox::boxes_fit<D>(t.x_lo, t.x_hi, t.y_lo, t.y_hi, t.Rlo, t.Rhi)) {
         if (active) adj_t2n4_pixel(a, t.x, t.y);
         return;
     }
@@ -521,7 +564,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_scatter_t2n4_box(AdjointArgs a) 
     }
     for (int i = threadIdx.x; i < 2 * cbox::kElems; i += 256) s_box[i] = 0;
     __syncthreads();
-    box_adj_all<0>(a, s_box, active, t, W);
+    box_adj_all<0, D>(a, s_box, active, t, W);
 }
 
 // Any factor count: per factor the narrow and wide boxes, 2^M box choices e
@@ -589,6 +632,7 @@ __global__ __launch_bounds__(256) void k_adj_finish(const int64_t *__restrict__ 
     }
 }
 
+#ifndef BSF_ADJOINT_FRAME1_UNIT
 }  // namespace
 
 int64_t fill_blocks(int64_t n) {
@@ -621,9 +665,12 @@ bsf_status run_adjoint_scatter(const Plan &p, const AdjointArgs &a, int32_t *sta
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)fill_blocks(n)), dim3(256), 0, st, a.Ghat, n);
     BSF_HIP_CHECK(hipGetLastError());
     if (p.n_dirs == 4 && p.order == 2 && p.tied && a.canon == 1)
-        hipLaunchKernelGGL(k_adj_scatter_t2n4_box, dim3((unsigned)xcd_grid((int64_t)grid.x * grid.y)), dim3(256), 0,
-                           st, a);
-    else if (p.n_dirs == 4 && p.order == 2 && p.tied)
+        hipLaunchKernelGGL(k_adj_scatter_t2n4_box<0>, dim3((unsigned)xcd_grid((int64_t)grid.x * grid.y)), dim3(256),
+                           0, st, a);
+    else if (p.n_dirs == 4 && p.order == 2 && p.tied && a.canon == 2) {
+        const bsf_status r = launch_adj_scatter_f1(a, dim3((unsigned)xcd_grid((int64_t)grid.x * grid.y)), st);
+        if (r != BSF_OK) return r;
+    } else if (p.n_dirs == 4 && p.order == 2 && p.tied)
         hipLaunchKernelGGL(k_adj_scatter_t2n4, grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(k_adj_scatter_generic, grid, dim3(256), 0, st, a);
@@ -641,3 +688,15 @@ bsf_status run_adjoint_finish(const Plan &p, const int64_t *Ghat, const int32_t 
 }
 
 }  // namespace bsf
+
+#else  // BSF_ADJOINT_FRAME1_UNIT: the cluster-box scatter of Table 1's directions
+}  // namespace
+
+bsf_status launch_adj_scatter_f1(const AdjointArgs &a, dim3 grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_scatter_t2n4_box<1>, grid, dim3(256), 0, st, a);
+    BSF_HIP_CHECK(hipGetLastError());
+    return BSF_OK;
+}
+
+}  // namespace bsf
+#endif

@@ -37,8 +37,8 @@ GEOMS = [(4096, 4096, 48.0), (37, 53, 9.0), (300, 17, 21.0), (1, 64, 15.0), (129
 # (frame, tile_w, tile_h, LDS rows): the forward kernel's 16 x 8 tiles with
 # 38-row boxes and 16 x 4 tiles with 18-row boxes, the adjoint's 16 x 16 tiles
 # with 48-row boxes; in the frame of Table 1's directions the forward's 16 x 8
-# tiles
-TILES = [(0, 16, 8, 38), (0, 16, 4, 18), (0, 16, 16, 48), (1, 16, 8, 38)]
+# tiles and the adjoint's 16 x 16
+TILES = [(0, 16, 8, 38), (0, 16, 4, 18), (0, 16, 16, 48), (1, 16, 8, 38), (1, 16, 16, 48)]
 DIRS = {0: ((1, 0), (0, 1), (1, 1), (1, -1)), 1: ((2, 1), (1, 2), (1, -2), (2, -1))}
 
 

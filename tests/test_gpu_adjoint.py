@@ -67,14 +67,20 @@ def test_gradients_match_oracle(order, tied, shape, hi, smooth):
     assert_grad_close(gs, rgs, what="grad_steps")
 
 
-def test_gradients_table1_directions():
-    """Step derivatives from the cluster-box kernel in the frame of Table 1's
-    directions, and the image gradient of the generic scatter, against the
-    oracle's analytic gradients."""
-    note("adjoint table1 directions")
+@pytest.mark.parametrize("shape,hi,smooth", [
+    ((44, 52), 11.0, True),
+    ((120, 136), 12.0, True),     # many tiles through the cluster boxes
+    ((61, 77), 9.0, False),       # independent steps: most tiles scatter pixel by pixel
+])
+def test_gradients_table1_directions(shape, hi, smooth):
+    """Step derivatives from the forward's cluster-box kernel in the frame of
+    Table 1's directions, and the image gradient from the adjoint's cluster-box
+    scatter in that frame (tiles whose boxes do not fit scatter each pixel's
+    taps to the window directly), against the oracle's analytic gradients."""
+    note("adjoint table1 directions", shape, smooth)
     dirs = ((2, 1), (1, 2), (1, -2), (2, -1))
-    img, steps, g = case((44, 52), 4, 1.0, 11.0, 71, smooth=True)
-    cfg = bsf.Config(dirs=dirs, order=2, max_step=11.0)
+    img, steps, g = case(shape, 4, 1.0, hi, 71, smooth=smooth)
+    cfg = bsf.Config(dirs=dirs, order=2, max_step=hi)
     out, gi, gs, ds = gpu_grads(cfg, img, steps, g)
     rgi, rgs = O.grad_real(img, dirs, 2, True, steps, g)
     assert_grad_close(gi, rgi, what="grad_img")
