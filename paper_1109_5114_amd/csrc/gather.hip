@@ -861,7 +861,7 @@ __host__ __device__ constexpr int f1_target(int C, int q, int j) {
     int idx = 0, bit = 0;
     for (int k = 0; k < 4; ++k) {
         const int c = cbox::cl(C, k), qk = k == 0 ? q % 3 : k == 1 ? (q / 3) % 3 : k == 2 ? (q / 9) % 3 : q / 27;
-        int o;
+        int o = 0;
         if (c == 1 && qk == 1) {
             o = ((j >> bit) & 1) ? 2 : 0;
             ++bit;
